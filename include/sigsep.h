@@ -1,0 +1,293 @@
+/*
+ * sigsep.h -- C ABI of the MI355X (gfx950) signal-separation library.
+ *
+ * The library implements the per-frame path of Kieffer et al., "Application
+ * of signal separation to diffraction image compression and serial
+ * crystallography" (2024):
+ *
+ *   raw Jungfrau words --ss_correct--> corrected intensity v = signal / norm
+ *   v --ss_sigma_clip (CSR regroup + iterative clipping)--> 1-D profile
+ *   v + profile --ss_compress / ss_peakfind / ss_classify--> kept pixels, peaks
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Pointers marked [dev] are device pointers, [host] host pointers.  The
+ *   caller owns every buffer; the library never allocates, frees or keeps a
+ *   pointer after the call returns.
+ * - Device calls enqueue kernels on `stream` and return at once; they never
+ *   synchronise.  Outputs are valid once the stream reaches that point.
+ * - Return value: SS_OK (0), or a negative code detected on the host before
+ *   anything was enqueued (SS_EINVAL, SS_ESIZE), or SS_EHIP when the HIP
+ *   runtime reported a launch error.  ss_strerror() names a code.
+ * - Frames are row-major [n_frames][n_pix] with pixel index y * width + x.
+ * - Masks are uint8, nonzero = masked.  A frame value that is not finite
+ *   (NaN/Inf, e.g. an invalid gain code) marks that pixel masked in that
+ *   frame only.
+ * - Statistics are accumulated in float64; frames are float32.
+ * - Calls on different streams are independent; calls that share output or
+ *   workspace buffers must be ordered by the caller.
+ */
+#ifndef SIGSEP_H
+#define SIGSEP_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SS_OK 0
+#define SS_EINVAL (-1) /* null pointer, bad flag or parameter out of range */
+#define SS_ESIZE (-2)  /* size out of range or capacity too small          */
+#define SS_EHIP (-3)   /* HIP runtime error at launch                       */
+
+/* Error models of Sec. 2.2 and 2.5. */
+#define SS_AZIMUTHAL 0 /* spread of the bin's values (eqs. varA, std2)       */
+#define SS_POISSON 1   /* counting statistics (eqs. poisson, varianceP, sem) */
+#define SS_HYBRID 2    /* clip with the azimuthal spread, report Poisson     */
+
+/* Pixel splitting of the CSR builder (Sec. 2.2, "Azimuthal averaging"). */
+#define SS_SPLIT_NONE 0
+#define SS_SPLIT_BBOX 1
+
+/* Radial coordinate code of a pixel (see ss_radial_coords). */
+#define SS_RC_FRAC_BITS 20
+#define SS_RC_MASKED 0xFFFFFFFFu
+#define SS_MAX_BINS 4094
+#define SS_MAX_ITER 32
+#define SS_MAX_PATCH 15
+
+/*
+ * Pixel-to-bin matrix in CSR form (rows = radial bins), Sec. 2.2: the
+ * regrouping is a sparse matrix times the flattened image.  weight[j] is the
+ * per-entry weight omega = c[i, r] * norm_i of eq. omega (the pixel's share
+ * of the bin times its normalisation factor).  Row entries have ascending
+ * pixel indices.  max_row is the length of the longest row.
+ */
+typedef struct {
+    int32_t n_bins;
+    int32_t max_row;
+    int64_t n_pix;
+    int64_t nnz;
+    const int64_t *indptr;  /* [dev] [n_bins + 1] */
+    const int32_t *indices; /* [dev] [nnz]        */
+    const float *weight;    /* [dev] [nnz]        */
+} ss_csr;
+
+/*
+ * Parameters of the path.
+ * cutoff    clipping threshold n of eq. clip; <= 0 selects Chauvenet's
+ *           value sqrt(2 ln(size / sqrt(2 pi))) per pass (eq. chauvenet)
+ * max_iter  maximum number of rejection passes K (Sec. 2.4), 0..SS_MAX_ITER
+ * error_model  SS_AZIMUTHAL, SS_POISSON or SS_HYBRID
+ * dark_var  sigma_dark^2 of eq. poisson, in signal units squared
+ * n_pick    sparsification threshold SNR_pick of Sec. 3
+ * noise     noise level added in quadrature to the background std (Sec. 4.1)
+ * snr       peak-finder SNR threshold (Sec. 4)
+ * patch     odd side P of the peak-finder's square patch, 1..SS_MAX_PATCH
+ * min_count minimum number of SNR-passing pixels in the patch
+ */
+typedef struct {
+    float cutoff;
+    int32_t max_iter;
+    int32_t error_model;
+    float dark_var;
+    float n_pick;
+    float noise;
+    float snr;
+    int32_t patch;
+    int32_t min_count;
+} ss_params;
+
+/*
+ * 1-D background profile, every array [dev] [n_frames][n_bins].
+ * mean = V / Omega (eq. weighted_avg); std = sqrt(VV / OmegaOmega) (eq. std2)
+ * or the Poisson std; sem = sqrt(VV) / Omega (eq. sem2) or the Poisson sem;
+ * sum_w = Omega (eq. omega); n_members = members of the final set; n_iter =
+ * rejection passes that removed something; converged = 1 when a pass removed
+ * nothing.  An empty bin has mean = std = sem = 0.
+ */
+typedef struct {
+    double *mean;
+    double *std;
+    double *sem;
+    double *sum_w;
+    int32_t *n_members;
+    int32_t *n_iter;
+    int32_t *converged;
+} ss_profile;
+
+/*
+ * Radial position of every pixel for the background lookup of Sec. 3 ("the
+ * distance to the centre of every pixel").  Bins are uniform: centre of bin r
+ * = centre0 + r * width.  rcoord[i] packs the interval t (bin centre t <=
+ * position < centre t+1, t = -1 below the first centre, n_bins - 1 beyond
+ * the last) as (t + 1) << SS_RC_FRAC_BITS, plus the position's fraction of
+ * that interval in the low SS_RC_FRAC_BITS bits; SS_RC_MASKED marks a
+ * statically masked pixel.
+ */
+typedef struct {
+    int32_t n_bins;
+    double centre0;
+    double width;
+    const uint32_t *rcoord; /* [dev] [n_pix] */
+} ss_radial;
+
+/* Peak record of Sec. 4: centroid (pixel units, centres at +0.5), sum of
+ * background-subtracted intensity and its propagated deviation. */
+typedef struct {
+    uint32_t index;
+    float y;
+    float x;
+    float intensity;
+    float sigma;
+} ss_peak;
+
+/* Name of a return code (static string). */
+const char *ss_strerror(int code);
+
+/* Library version as major * 10000 + minor * 100 + patch. */
+int ss_version(void);
+
+/*
+ * ss_build_csr [host] -- the CSR of Sec. 2.2 for a flat detector normal to
+ * the beam.  Pixel (y, x) covers [y, y+1) x [x, x+1) in pixel units, the
+ * beam centre is (centre_row, centre_col) in the same units, 2theta =
+ * atan(pixel_m * r / dist_m) in degrees, and the n_bins bins are uniform on
+ * [0, 2theta_max] with 2theta_max the largest pixel-corner angle.
+ * split = SS_SPLIT_NONE: a pixel goes whole to the bin of its centre angle.
+ * split = SS_SPLIT_BBOX: a pixel spans [min, max] of its corner angles (0 for
+ * the pixel holding the beam centre) and c[i, r] = overlap / span; the
+ * coefficients of a pixel sum to 1.  Masked pixels (mask [host] [n_pix],
+ * may be NULL) get no entries.  weight = c * norm (norm [host] [n_pix], NULL
+ * means 1).
+ * Call once with indices == NULL to get *nnz and *max_row, then again with
+ * indptr [n_bins + 1], indices and weight [capacity >= nnz] to fill them.
+ * *tth_max receives 2theta_max in degrees.  Errors: SS_EINVAL, SS_ESIZE.
+ */
+int ss_build_csr(int32_t height, int32_t width, double pixel_m, double dist_m,
+                 double centre_row, double centre_col, int32_t n_bins, int32_t split,
+                 const uint8_t *mask, const float *norm,
+                 int64_t *indptr, int32_t *indices, float *weight, int64_t capacity,
+                 int64_t *nnz, int32_t *max_row, double *tth_max);
+
+/*
+ * ss_radial_coords [host] -- rcoord [host] [n_pix] of the pixel-centre
+ * angles for the bins of ss_build_csr (same geometry, n_bins and tth_max);
+ * masked pixels (mask may be NULL) get SS_RC_MASKED.  *centre0 and *width
+ * receive the first bin centre and the bin width.  Errors: SS_EINVAL,
+ * SS_ESIZE (n_bins > SS_MAX_BINS).
+ */
+int ss_radial_coords(int32_t height, int32_t width, double pixel_m, double dist_m,
+                     double centre_row, double centre_col, int32_t n_bins, double tth_max,
+                     const uint8_t *mask, uint32_t *rcoord, double *centre0, double *width_out);
+
+/*
+ * ss_correct -- Jungfrau pre-processing (Sec. 1.2) and normalisation
+ * (eq. norm).  Word bits 15..14 select the gain level (00 -> 0, 01 -> 1,
+ * 11 -> 2; 10 is invalid), bits 13..0 are the ADC value; signal = (ADC -
+ * pedestal[g]) / gain[g] (float64 arithmetic, rounded to float32, the 32-bit
+ * pre-processed frame), then out = signal / norm (float64, rounded to
+ * float32).  Invalid words give NaN and are counted.
+ *   raw       [dev] uint16 [n_frames][n_pix]
+ *   pedestal  [dev] float  [3][n_pix]   (ADU)
+ *   gain      [dev] float  [3][n_pix]   (ADU per photon)
+ *   norm      [dev] float  [n_pix] or NULL (= 1)
+ *   out       [dev] float  [n_frames][n_pix]
+ *   n_invalid [dev] int64  [n_frames] or NULL; overwritten
+ * Errors: SS_EINVAL (null required pointer), SS_ESIZE (n_pix < 0 or
+ * >= 2^31, n_frames < 0), SS_EHIP.
+ */
+int ss_correct(const uint16_t *raw, int32_t n_frames, int64_t n_pix,
+               const float *pedestal, const float *gain, const float *norm,
+               float *out, int64_t *n_invalid, hipStream_t stream);
+
+/*
+ * ss_integrate -- azimuthal average with uncertainties (Sec. 2.2, eqs. avg
+ * to sem2), no clipping: ss_sigma_clip with max_iter forced to 0.
+ */
+int ss_integrate(const float *frames, const float *norm, const uint8_t *mask,
+                 int32_t n_frames, const ss_csr *csr, const ss_params *params,
+                 const ss_profile *out, hipStream_t stream);
+
+/*
+ * ss_sigma_clip -- per-bin iterative sigma-clipping (eq. clip, Sec. 2.4).
+ * For every frame and bin: members = CSR entries whose pixel is unmasked
+ * and finite, value v = frames[f][i], weight omega = csr weight.  Passes
+ * k = 0 .. max_iter-1 compute the statistics of the current set and remove
+ * members with |v - mean| > n * std (strict; n = cutoff or Chauvenet's value
+ * for the current size); the loop stops at the first pass that removes
+ * nothing.  The profile holds the statistics of the final set.
+ *   frames [dev] float [n_frames][csr->n_pix] (corrected intensities v)
+ *   norm   [dev] float [n_pix] or NULL; used only by the Poisson and hybrid
+ *          models, whose pixel variance is (max(v * norm, 0) + dark_var) /
+ *          norm^2 in units of v
+ *   mask   [dev] uint8 [n_pix] or NULL (in addition to the CSR's own mask)
+ *   csr, params, out: [host] structs; their arrays are [dev]
+ * Errors: SS_EINVAL, SS_ESIZE (n_bins > SS_MAX_BINS, max_iter out of range),
+ * SS_EHIP.
+ */
+int ss_sigma_clip(const float *frames, const float *norm, const uint8_t *mask,
+                  int32_t n_frames, const ss_csr *csr, const ss_params *params,
+                  const ss_profile *out, hipStream_t stream);
+
+/*
+ * Workspace (device bytes) needed by ss_classify / ss_compress /
+ * ss_peakfind for n_frames frames of n_pix pixels and n_bins bins.
+ */
+size_t ss_classify_workspace(int32_t n_frames, int64_t n_pix, int32_t n_bins);
+
+/*
+ * ss_classify -- per-pixel classification against the clipped profile,
+ * feeding both applications in one pass over the pixels.
+ * Background of pixel i (Sec. 3): mu_i, sigma_i = the profile's mean and std
+ * linearly interpolated between the centres of the non-empty bins at the
+ * pixel's angle, constant beyond the first and last; sigma_eff =
+ * sqrt(sigma_i^2 + noise^2).
+ * Sparsification (Sec. 3): keep i when unmasked and v_i - mu_i > n_pick *
+ * sigma_eff; kept_index / kept_value receive (i, v_i) in ascending i,
+ * [dev] [n_frames][capacity]; n_kept [dev] int64 [n_frames] receives the
+ * true count, entries beyond capacity are dropped.
+ * Peak finder (Sec. 4): candidate = unmasked and v - mu >= snr * sigma_eff;
+ * a peak is a candidate that is the maximum of v over the unmasked pixels
+ * of the patch x patch square centred on it (clipped at the border; ties go
+ * to the lower index) with at least min_count candidates in the square.
+ * Record over the square's candidates j: w_j = v_j - mu_j, intensity =
+ * sum w_j, sigma = sqrt(sum sigma_eff_j^2), centroid = sum w_j (y_j + 0.5,
+ * x_j + 0.5) / sum w_j.  peaks [dev] [n_frames][peak_capacity] in ascending
+ * index; n_peaks [dev] int64 [n_frames] (true count).
+ * Either output group may be disabled by passing NULL for all its pointers.
+ *   frames [dev] float [n_frames][height * width]; mask [dev] or NULL
+ *   radial, profile, params: [host] structs with [dev] arrays
+ *   workspace [dev] >= ss_classify_workspace(...) bytes
+ * Errors: SS_EINVAL, SS_ESIZE (workspace too small, capacities < 0,
+ * bin count mismatch), SS_EHIP.
+ */
+int ss_classify(const float *frames, const uint8_t *mask, int32_t n_frames,
+                int32_t height, int32_t width, const ss_radial *radial,
+                const ss_profile *profile, const ss_params *params,
+                uint32_t *kept_index, float *kept_value, int64_t capacity, int64_t *n_kept,
+                ss_peak *peaks, int64_t peak_capacity, int64_t *n_peaks,
+                void *workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* ss_compress -- the sparsification half of ss_classify (Sec. 3). */
+int ss_compress(const float *frames, const uint8_t *mask, int32_t n_frames,
+                int32_t height, int32_t width, const ss_radial *radial,
+                const ss_profile *profile, const ss_params *params,
+                uint32_t *kept_index, float *kept_value, int64_t capacity, int64_t *n_kept,
+                void *workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* ss_peakfind -- the peak-finder half of ss_classify (Sec. 4). */
+int ss_peakfind(const float *frames, const uint8_t *mask, int32_t n_frames,
+                int32_t height, int32_t width, const ss_radial *radial,
+                const ss_profile *profile, const ss_params *params,
+                ss_peak *peaks, int64_t peak_capacity, int64_t *n_peaks,
+                void *workspace, size_t workspace_bytes, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SIGSEP_H */

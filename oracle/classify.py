@@ -8,8 +8,8 @@ beyond the first and last non-empty bins (``numpy.interp``).  The same
 mu_i, sigma_i serve sparsification, densification and the peak finder.
 sigma_eff = sqrt(sigma^2 + noise^2), with the noise level of Sec. 4.1.
 
-Values are in corrected-intensity units v = signal / norm (eq. norm), the
-units of the stored profile.
+Frames hold the corrected intensity v = signal / norm of eq. norm, the units
+of the stored profile; kept values and peak intensities are in those units.
 
 Sparsification (Sec. 3): keep pixel i when it is valid (not masked, finite)
 and v_i - mu_i > n_pick * sigma_eff_i (strict, one-sided: low outliers are
@@ -50,21 +50,20 @@ def background_at(position, centres, profile):
     return mu, sd
 
 
-def pixel_state(signal, norm, mask, position, centres, profile, noise=0.0):
+def pixel_state(frame, mask, position, centres, profile, noise=0.0):
     """v, mu, sigma_eff and validity for every pixel of one frame (flat arrays)."""
-    s = np.asarray(signal, dtype=np.float64).reshape(-1)
-    nr = np.ones(s.size) if norm is None else np.asarray(norm, dtype=np.float64).reshape(-1)
+    s = np.asarray(frame, dtype=np.float64).reshape(-1)
     valid = np.isfinite(s)
     if mask is not None:
         valid &= np.asarray(mask).reshape(-1) == 0
-    v = np.where(valid, s / nr, 0.0)
+    v = np.where(valid, s, 0.0)
     mu, sd = background_at(position, centres, profile)
     return v, mu, np.sqrt(sd * sd + noise * noise), valid
 
 
-def compress(signal, norm, mask, position, centres, profile, n_pick=3.0, noise=0.0):
+def compress(frame, mask, position, centres, profile, n_pick=3.0, noise=0.0):
     """Sparse frame: (indices int64 ascending, values float64 = v)."""
-    v, mu, se, valid = pixel_state(signal, norm, mask, position, centres, profile, noise)
+    v, mu, se, valid = pixel_state(frame, mask, position, centres, profile, noise)
     keep = valid & (v - mu > n_pick * se)
     idx = np.nonzero(keep)[0]
     return idx, v[idx]
@@ -91,10 +90,10 @@ def _shift(a, dy, dx, fill):
     return out
 
 
-def peakfind(signal, norm, mask, height, width, position, centres, profile,
+def peakfind(frame, mask, height, width, position, centres, profile,
              snr=3.0, patch=3, min_count=3, noise=0.0):
     """Peaks of one frame as a structured array (PEAK_DTYPE), ascending index."""
-    v, mu, se, valid = pixel_state(signal, norm, mask, position, centres, profile, noise)
+    v, mu, se, valid = pixel_state(frame, mask, position, centres, profile, noise)
     H, W = height, width
     cand = valid & (v - mu >= snr * se)
     V = v.reshape(H, W)
@@ -138,10 +137,10 @@ def peakfind(signal, norm, mask, height, width, position, centres, profile,
     return out
 
 
-def peakfind_loops(signal, norm, mask, height, width, position, centres, profile,
+def peakfind_loops(frame, mask, height, width, position, centres, profile,
                    snr=3.0, patch=3, min_count=3, noise=0.0):
     """The same peak rule with explicit Python loops (small frames only)."""
-    v, mu, se, valid = pixel_state(signal, norm, mask, position, centres, profile, noise)
+    v, mu, se, valid = pixel_state(frame, mask, position, centres, profile, noise)
     H, W = height, width
     cand = valid & (v - mu >= snr * se)
     h = patch // 2

@@ -12,6 +12,10 @@ reference, so this is a reading, **parity unpinned** against the paper:
   signal is in photons (the dark-current subtraction of eq. norm);
 * the corrected frame is stored as float32, the precision the paper gives
   for pre-processed data; the arithmetic before that rounding is float64.
+
+``normalise`` then applies the normalisation of eq. norm, I = signal / norm,
+again in float64 and stored as a float32 frame: this corrected-intensity
+frame is what the later stages consume.
 """
 
 from __future__ import annotations
@@ -44,3 +48,11 @@ def correct(raw: np.ndarray, pedestal: np.ndarray, gain: np.ndarray):
     signal = (adc.astype(np.float64) - ped) / gn
     signal[invalid] = np.nan
     return signal.astype(np.float32).reshape(shape), invalid.reshape(shape)
+
+
+def normalise(signal: np.ndarray, norm=None) -> np.ndarray:
+    """Corrected intensity I = signal / norm (eq. norm) as a float32 frame."""
+    s = np.asarray(signal, dtype=np.float64)
+    if norm is None:
+        return s.astype(np.float32)
+    return (s / np.asarray(norm, dtype=np.float64)).astype(np.float32)

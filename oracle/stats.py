@@ -1,7 +1,9 @@
 """Per-bin weighted statistics and iterative sigma-clipping (FP64).
 
 Sec. 2.2 defines, for the members of one radial bin (pixel i with CSR
-coefficient c and normalisation norm_i):
+coefficient c and normalisation norm_i).  The frames handed to these
+functions hold the corrected intensity v = signal / norm of eq. norm; norm
+itself enters through the weights and the Poisson variance only.
 
   weight       omega_i = c * norm_i                          (eq. omega)
   value        v_i = signal_i / norm_i                       (eq. norm)
@@ -81,58 +83,70 @@ def moments(v, omega, pvar=None):
     return out
 
 
-def bin_members(signal, norm, csr, r, mask=None, dark_var=0.0):
+def bin_members(frame, norm, csr, r, mask=None, dark_var=0.0):
     """Members of bin r for one frame: (pixel, c, v, omega, c^2 sigma^2).
 
-    A pixel is a member when it is not masked and its signal is finite.
+    frame holds v = signal / norm.  A pixel is a member when it is not
+    masked and its value is finite.  sigma^2 is the variance of the pixel's
+    signal, max(v * norm, 0) + sigma_dark^2.
     """
     pix, c = csr.row(r)
-    s = signal[pix].astype(np.float64)
+    v = frame[pix].astype(np.float64)
     nr = np.ones(pix.size) if norm is None else norm[pix].astype(np.float64)
-    ok = np.isfinite(s)
+    ok = np.isfinite(v)
     if mask is not None:
         ok &= mask[pix] == 0
-    pix, c, s, nr = pix[ok], c[ok], s[ok], nr[ok]
-    var = np.maximum(s, 0.0) + dark_var
-    return pix, c, s / nr, c * nr, c * c * var
+    pix, c, v, nr = pix[ok], c[ok], v[ok], nr[ok]
+    var = np.maximum(v * nr, 0.0) + dark_var
+    return pix, c, v, c * nr, c * c * var
 
 
 def _clip_bin(v, omega, pvar, cutoff, max_iter, model):
     keep = np.ones(v.size, dtype=bool)
-    n_iter, converged = 0, 0
+    n_iter, converged, margin = 0, 0, np.inf
     for _ in range(max_iter):
         m = moments(v[keep], omega[keep], pvar[keep])
         n = cutoff if cutoff > 0 else chauvenet(int(keep.sum()))
         spread = m["std_p"] if model == POISSON else m["std"]
-        drop = keep & (np.abs(v - m["mean"]) > n * spread)
+        thr = n * spread
+        dev = np.abs(v - m["mean"])
+        if keep.any() and np.isfinite(thr) and thr > 0:
+            margin = min(margin, float(np.min(np.abs(dev[keep] - thr))) / thr)
+        drop = keep & (dev > thr)
         if not drop.any():
             converged = 1
             break
         keep &= ~drop
         n_iter += 1
-    return keep, n_iter, converged
+    return keep, n_iter, converged, margin
 
 
-def sigma_clip(signal, norm, csr, mask=None, cutoff=3.0, max_iter=5,
-               error_model=AZIMUTHAL, dark_var=0.0, return_keep=False):
+def sigma_clip(frame, norm, csr, mask=None, cutoff=3.0, max_iter=5,
+               error_model=AZIMUTHAL, dark_var=0.0, return_keep=False, return_margin=False):
     """Sigma-clipped profile of one frame (max_iter = 0 gives the plain average).
 
-    signal: float [N] (NaN = invalid); norm: float [N] or None (= 1).
+    frame: corrected intensity v = signal / norm, float [N] (NaN = invalid);
+    norm: float [N] or None (= 1), for the weights and the Poisson variance.
+    With ``return_margin`` also ``margin``: per bin, the smallest relative
+    distance | |v - mean_k| - n_k std_k | / (n_k std_k) of any member to the
+    threshold over the passes run (inf when no pass compared anything); it
+    marks bins whose clip decisions sit on the threshold within rounding.
     Returns dict of per-bin arrays: mean, std, sem, sum_w (Omega), n_members,
     n_iter, converged; with ``return_keep`` also the per-entry kept flags of
     every bin (list of bool arrays aligned with the members of that bin).
     """
     nb = csr.n_bins
-    signal = np.asarray(signal).reshape(-1)
+    frame = np.asarray(frame).reshape(-1)
     norm = None if norm is None else np.asarray(norm).reshape(-1)
     mask = None if mask is None else np.asarray(mask).reshape(-1)
     out = dict(mean=np.zeros(nb), std=np.zeros(nb), sem=np.zeros(nb), sum_w=np.zeros(nb),
                n_members=np.zeros(nb, dtype=np.int64), n_iter=np.zeros(nb, dtype=np.int64),
                converged=np.zeros(nb, dtype=np.int64))
     keeps = []
+    margins = np.full(nb, np.inf)
     for r in range(nb):
-        pix, c, v, omega, pvar = bin_members(signal, norm, csr, r, mask, dark_var)
-        keep, n_iter, conv = _clip_bin(v, omega, pvar, cutoff, max_iter, error_model)
+        pix, c, v, omega, pvar = bin_members(frame, norm, csr, r, mask, dark_var)
+        keep, n_iter, conv, margins[r] = _clip_bin(v, omega, pvar, cutoff, max_iter, error_model)
         m = moments(v[keep], omega[keep], pvar[keep])
         poisson_report = error_model in (POISSON, HYBRID)
         out["mean"][r] = m["mean"]
@@ -146,10 +160,12 @@ def sigma_clip(signal, norm, csr, mask=None, cutoff=3.0, max_iter=5,
             keeps.append((pix, keep))
     if return_keep:
         out["keep"] = keeps
+    if return_margin:
+        out["margin"] = margins
     return out
 
 
-def integrate(signal, norm, csr, mask=None, error_model=AZIMUTHAL, dark_var=0.0):
+def integrate(frame, norm, csr, mask=None, error_model=AZIMUTHAL, dark_var=0.0):
     """Azimuthal average with uncertainties, no clipping (eqs. avg .. sem2)."""
-    return sigma_clip(signal, norm, csr, mask, cutoff=3.0, max_iter=0,
+    return sigma_clip(frame, norm, csr, mask, cutoff=3.0, max_iter=0,
                       error_model=error_model, dark_var=dark_var)

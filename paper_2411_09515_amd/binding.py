@@ -1,0 +1,117 @@
+"""ctypes binding of libsigsep.so (argument marshalling only).
+
+Every function takes torch tensors for device buffers, passes their data
+pointers and the current HIP stream to the C ABI declared in
+``include/sigsep.h``, and raises ``SigsepError`` on a nonzero return code.
+There is no fallback: if the library is missing the import fails loudly.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "_lib", "libsigsep.so")
+
+SS_OK, SS_EINVAL, SS_ESIZE, SS_EHIP = 0, -1, -2, -3
+SS_AZIMUTHAL, SS_POISSON, SS_HYBRID = 0, 1, 2
+SS_SPLIT_NONE, SS_SPLIT_BBOX = 0, 1
+SS_RC_FRAC_BITS = 20
+SS_RC_MASKED = 0xFFFFFFFF
+SS_MAX_BINS = 4094
+SS_MAX_ITER = 32
+SS_MAX_PATCH = 15
+
+EXPORTED = (
+    "ss_strerror", "ss_version", "ss_build_csr", "ss_radial_coords", "ss_correct",
+    "ss_integrate", "ss_sigma_clip", "ss_classify_workspace", "ss_classify",
+    "ss_compress", "ss_peakfind",
+)
+
+
+class SigsepError(RuntimeError):
+    def __init__(self, name, code):
+        super().__init__(f"{name} failed: {code} ({strerror(code)})")
+        self.code = code
+
+
+class Csr(ctypes.Structure):
+    _fields_ = [("n_bins", ctypes.c_int32), ("max_row", ctypes.c_int32), ("n_pix", ctypes.c_int64),
+                ("nnz", ctypes.c_int64), ("indptr", ctypes.c_void_p), ("indices", ctypes.c_void_p),
+                ("weight", ctypes.c_void_p)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("cutoff", ctypes.c_float), ("max_iter", ctypes.c_int32), ("error_model", ctypes.c_int32),
+                ("dark_var", ctypes.c_float), ("n_pick", ctypes.c_float), ("noise", ctypes.c_float),
+                ("snr", ctypes.c_float), ("patch", ctypes.c_int32), ("min_count", ctypes.c_int32)]
+
+
+class Profile(ctypes.Structure):
+    _fields_ = [("mean", ctypes.c_void_p), ("std", ctypes.c_void_p), ("sem", ctypes.c_void_p),
+                ("sum_w", ctypes.c_void_p), ("n_members", ctypes.c_void_p), ("n_iter", ctypes.c_void_p),
+                ("converged", ctypes.c_void_p)]
+
+
+class Radial(ctypes.Structure):
+    _fields_ = [("n_bins", ctypes.c_int32), ("centre0", ctypes.c_double), ("width", ctypes.c_double),
+                ("rcoord", ctypes.c_void_p)]
+
+
+class Peak(ctypes.Structure):
+    _fields_ = [("index", ctypes.c_uint32), ("y", ctypes.c_float), ("x", ctypes.c_float),
+                ("intensity", ctypes.c_float), ("sigma", ctypes.c_float)]
+
+
+PEAK_BYTES = ctypes.sizeof(Peak)
+
+_lib = None
+
+
+def lib():
+    """The loaded library (loads it on first use; raises if it is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2411_09515_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, f64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
+        P = ctypes.POINTER
+        L.ss_strerror.restype = ctypes.c_char_p
+        L.ss_strerror.argtypes = [ctypes.c_int]
+        L.ss_version.restype = ctypes.c_int
+        L.ss_version.argtypes = []
+        L.ss_build_csr.restype = ctypes.c_int
+        L.ss_build_csr.argtypes = [i32, i32, f64, f64, f64, f64, i32, i32, vp, vp, vp, vp, vp, i64,
+                                   P(i64), P(i32), P(f64)]
+        L.ss_radial_coords.restype = ctypes.c_int
+        L.ss_radial_coords.argtypes = [i32, i32, f64, f64, f64, f64, i32, f64, vp, vp, P(f64), P(f64)]
+        L.ss_correct.restype = ctypes.c_int
+        L.ss_correct.argtypes = [vp, i32, i64, vp, vp, vp, vp, vp, vp]
+        for name in ("ss_integrate", "ss_sigma_clip"):
+            fn = getattr(L, name)
+            fn.restype = ctypes.c_int
+            fn.argtypes = [vp, vp, vp, i32, P(Csr), P(Params), P(Profile), vp]
+        L.ss_classify_workspace.restype = sz
+        L.ss_classify_workspace.argtypes = [i32, i64, i32]
+        L.ss_classify.restype = ctypes.c_int
+        L.ss_classify.argtypes = [vp, vp, i32, i32, i32, P(Radial), P(Profile), P(Params), vp, vp, i64, vp,
+                                  vp, i64, vp, vp, sz, vp]
+        L.ss_compress.restype = ctypes.c_int
+        L.ss_compress.argtypes = [vp, vp, i32, i32, i32, P(Radial), P(Profile), P(Params), vp, vp, i64, vp,
+                                  vp, sz, vp]
+        L.ss_peakfind.restype = ctypes.c_int
+        L.ss_peakfind.argtypes = [vp, vp, i32, i32, i32, P(Radial), P(Profile), P(Params), vp, i64, vp,
+                                  vp, sz, vp]
+        _lib = L
+    return _lib
+
+
+def strerror(code: int) -> str:
+    return lib().ss_strerror(code).decode()
+
+
+def check(name: str, code: int) -> None:
+    if code != SS_OK:
+        raise SigsepError(name, code)

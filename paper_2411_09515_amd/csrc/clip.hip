@@ -1,0 +1,580 @@
+// Per-bin weighted statistics and iterative sigma-clipping (Sec. 2.2-2.5).
+//
+// One work-group owns one (bin, frame) pair.  Moments are float64 sums of
+// shifted deviations d = v - K of the members (value v, weight omega):
+//   S_w = sum omega, S_wd = sum omega d, S_w2 = sum omega^2,
+//   S_w2d = sum omega^2 d, S_w2d2 = sum omega^2 d^2, S_pv = sum omega^2 var_v,
+// so that mean = K + S_wd / S_w and, with delta = S_wd / S_w,
+//   VV = S_w2d2 - 2 delta S_w2d + delta^2 S_w2     (= sum omega^2 (v - mean)^2).
+// The first evaluation is a true two-pass: one sweep gives the mean, a second
+// sweep accumulates around K = that mean, so VV is well conditioned.  Every
+// rejection pass then accumulates only the members it removes and subtracts
+// them from the sums, so a pass costs one compare per member plus one
+// work-group reduction.
+//
+// Two kernels share that arithmetic and the clip decision:
+// * k_clip_regs keeps each member's value in registers (EPT per thread) and
+//   re-reads a weight only when its member is removed.  Azimuthal model, no
+//   extra mask, rows up to BLOCK * EPT entries: the hot path.
+// * k_clip_stream keeps nothing on chip: every pass re-gathers the row and
+//   replays the earlier passes' decisions from a (mean, threshold) history.
+//   It serves the Poisson and hybrid models, an extra mask and rows of any
+//   length.
+
+#include <cmath>
+
+#include "common.h"
+
+namespace ss {
+namespace {
+
+enum { S_W = 0, S_WD, S_W2, S_W2D, S_W2D2, S_PV, S_N, NSUM };
+
+struct ClipArgs {
+    const float *frames;
+    int64_t n_pix;
+    const float *norm;
+    const uint8_t *mask;
+    int32_t n_frames;
+    int32_t n_bins;
+    const int64_t *indptr;
+    const int32_t *indices;
+    const float *weight;
+    int64_t nnz;
+    double cutoff;
+    int32_t max_iter;
+    int32_t model;
+    double dark_var;
+    double *mean;
+    double *std;
+    double *sem;
+    double *sum_w;
+    int32_t *n_members;
+    int32_t *n_iter;
+    int32_t *converged;
+};
+
+struct Stats {
+    double mean, std, sem, pstd, psem;
+};
+
+__device__ inline Stats stats_from(const double (&s)[NSUM], double K) {
+    Stats st{0.0, 0.0, 0.0, 0.0, 0.0};
+    if (s[S_N] < 0.5 || !(s[S_W] > 0.0)) return st;
+    const double delta = s[S_WD] / s[S_W];
+    double vv = s[S_W2D2] - 2.0 * delta * s[S_W2D] + delta * delta * s[S_W2];
+    vv = vv > 0.0 ? vv : 0.0;
+    const double pv = s[S_PV] > 0.0 ? s[S_PV] : 0.0;
+    st.mean = K + delta;
+    st.std = sqrt(vv / s[S_W2]);
+    st.sem = sqrt(vv) / s[S_W];
+    st.pstd = sqrt(pv / s[S_W2]);
+    st.psem = sqrt(pv) / s[S_W];
+    return st;
+}
+
+// Pixel variance in units of v for the Poisson model (eq. poisson):
+// (max(signal, 0) + sigma_dark^2) / norm^2 with signal = v * norm.
+__device__ inline double poisson_var(float v, float nrm, double dark_var) {
+    const double s = double(v) * double(nrm);
+    return ((s > 0.0 ? s : 0.0) + dark_var) / (double(nrm) * double(nrm));
+}
+
+// Value of pixel idx, or NaN (not a member) when idx is outside the frame.
+__device__ inline float gather(const float *__restrict__ fr, int32_t idx, int64_t n_pix) {
+    return uint64_t(uint32_t(idx)) < uint64_t(n_pix) ? fr[idx] : __builtin_nanf("");
+}
+
+__device__ inline bool member_ok(float x, float w, const uint8_t *mask, int32_t idx) {
+    return isfinite(x) && w > 0.0f && !(mask && mask[idx]);
+}
+
+// The clip decision of eq. clip (strict, two-sided).
+__device__ inline bool clipped(float x, double mean, double thr) {
+    return fabs(double(x) - mean) > thr;
+}
+
+// Cut-off of pass k: the fixed value, or Chauvenet's value for the current
+// size (eq. chauvenet); <= 0 means nothing can be removed.
+__device__ inline double cutoff_for(double cutoff, double size) {
+    if (cutoff > 0.0) return cutoff;
+    constexpr double kSqrt2Pi = 2.5066282746310002;
+    return size > kSqrt2Pi ? sqrt(2.0 * log(size / kSqrt2Pi)) : -1.0;
+}
+
+// The running sums are decremented as members leave.  When the variance they
+// imply has lost more than about six of float64's sixteen digits to
+// cancellation (aggressive cut-offs shrink the spread by orders of magnitude
+// over many passes), they are re-accumulated around the current mean.
+__device__ inline bool needs_refresh(const double (&s)[NSUM]) {
+    if (s[S_N] < 0.5 || !(s[S_W] > 0.0)) return false;
+    const double delta = s[S_WD] / s[S_W];
+    const double mag = s[S_W2D2] + delta * delta * s[S_W2];
+    const double vv = s[S_W2D2] - 2.0 * delta * s[S_W2D] + delta * delta * s[S_W2];
+    return mag > 0.0 && !(vv > 1e-6 * mag);
+}
+
+__device__ inline void add_member(double (&s)[NSUM], double w, double d, double pv) {
+    const double w2 = w * w;
+    s[S_W] += w;
+    s[S_WD] += w * d;
+    s[S_W2] += w2;
+    s[S_W2D] += w2 * d;
+    s[S_W2D2] += w2 * d * d;
+    s[S_PV] += w2 * pv;
+    s[S_N] += 1.0;
+}
+
+__device__ inline void row_bounds(const ClipArgs &a, int bin, int64_t &start, int64_t &end) {
+    // clamped to [0, nnz] so a malformed indptr cannot read past the arrays
+    end = min(max(a.indptr[bin + 1], int64_t(0)), a.nnz);
+    start = min(max(a.indptr[bin], int64_t(0)), end);
+}
+
+__device__ inline void write_profile(const ClipArgs &a, int f, int bin, const double (&s)[NSUM], const Stats &st,
+                                     int n_iter, int converged) {
+    const int64_t o = int64_t(f) * a.n_bins + bin;
+    const bool report_poisson = a.model != SS_AZIMUTHAL;
+    const bool empty = s[S_N] < 0.5;
+    a.mean[o] = empty ? 0.0 : st.mean;
+    a.std[o] = empty ? 0.0 : (report_poisson ? st.pstd : st.std);
+    a.sem[o] = empty ? 0.0 : (report_poisson ? st.psem : st.sem);
+    a.sum_w[o] = empty ? 0.0 : s[S_W];
+    a.n_members[o] = int32_t(s[S_N]);
+    a.n_iter[o] = n_iter;
+    a.converged[o] = converged;
+}
+
+// Shift for the first sweep: the row's first value (any value near the data
+// keeps the sums well scaled).
+__device__ inline double first_shift(const ClipArgs &a, const float *fr, int64_t start, int64_t end) {
+    if (end <= start) return 0.0;
+    const float x0 = gather(fr, a.indices[start], a.n_pix);
+    return isfinite(x0) ? double(x0) : 0.0;
+}
+
+// ---------------------------------------------------------------------------
+
+// Pass control, computed by one thread and published to the work-group.
+struct PassCtl {
+    double mean, thr, K;
+    int go, n_iter, converged, refresh;
+};
+
+// Bookkeeping after rejection pass: stop when it removed nothing.
+__device__ inline void after_pass(PassCtl &c, bool removed_any) {
+    if (!removed_any) {
+        c.converged = 1;
+        c.go = 0;
+    } else {
+        c.n_iter += 1;
+    }
+}
+
+// Plan pass k_next from the running sums: a refresh of the sums when they
+// have lost precision, otherwise the next (mean, threshold), or stop.
+__device__ inline void plan(const ClipArgs &a, const double (&s)[NSUM], PassCtl &c, int k_next, bool allow_refresh) {
+    const Stats st = stats_from(s, c.K);
+    c.mean = st.mean;
+    c.refresh = 0;
+    if (allow_refresh && needs_refresh(s)) {
+        c.refresh = 1;
+        c.go = 1;
+        return;
+    }
+    if (k_next >= a.max_iter) {
+        c.go = 0;
+        return;
+    }
+    const double ncut = cutoff_for(a.cutoff, s[S_N]);
+    if (!(ncut > 0.0)) {
+        c.converged = 1;
+        c.go = 0;
+        return;
+    }
+    c.thr = ncut * ((a.model == SS_POISSON) ? st.pstd : st.std);
+    c.go = 1;
+}
+
+__device__ inline void load_state(const double *state, double (&s)[NSUM]) {
+#pragma unroll
+    for (int q = 0; q < NSUM; ++q) s[q] = state[q];
+}
+
+template <int BLOCK, int EPT>
+__global__ __launch_bounds__(BLOCK) void k_clip_regs(ClipArgs a) {
+    static_assert(EPT <= 64, "member flags live in one 64-bit word");
+    constexpr int NW = BLOCK / kWave;
+    __shared__ double part[NSUM * NW];
+    __shared__ double tot[NSUM];
+    __shared__ double state[NSUM];
+    __shared__ PassCtl ctl;
+
+    const int bin = int(blockIdx.x / uint32_t(a.n_frames));
+    const int f = int(blockIdx.x % uint32_t(a.n_frames));
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+    const int wid = tid / kWave;
+    int64_t start, end;
+    row_bounds(a, bin, start, end);
+    const int len = int(end - start);
+    const int32_t *__restrict__ idxs = a.indices + start;
+    const float *__restrict__ wts = a.weight + start;
+    const float *__restrict__ fr = a.frames + int64_t(f) * a.n_pix;
+
+    if (len == 0) {
+        if (tid == 0) {
+            const double z[NSUM] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+            write_profile(a, f, bin, z, Stats{0.0, 0.0, 0.0, 0.0, 0.0}, 0, a.max_iter > 0 ? 1 : 0);
+        }
+        return;
+    }
+    const uint32_t last = uint32_t(a.n_pix - 1);
+
+    float v[EPT];
+    uint64_t act = 0;
+    double K = first_shift(a, fr, start, end);
+
+    // Buffer views of the row and of the frame: every load below is issued
+    // unconditionally (slots past the row end read 0 and are masked after),
+    // so all EPT gathers of a thread can be in flight together, with one
+    // 32-bit offset register per slot and the slot's stride in a scalar.
+    const __amdgpu_buffer_rsrc_t ri = buffer_rsrc(idxs, uint32_t(len) * 4u);
+    const __amdgpu_buffer_rsrc_t rw = buffer_rsrc(wts, uint32_t(len) * 4u);
+    const __amdgpu_buffer_rsrc_t rf = buffer_rsrc(fr, uint32_t(a.n_pix) * 4u);
+    const uint32_t tofs = uint32_t(tid) * 4u;
+
+    // sweep 1: gather, Omega, first mean
+    {
+        int32_t ix[EPT];
+        float wt[EPT];
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            ix[e] = buffer_load_i32(ri, tofs, uint32_t(e * BLOCK) * 4u);
+            wt[e] = buffer_load_f32(rw, tofs, uint32_t(e * BLOCK) * 4u);
+        }
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) v[e] = buffer_load_f32(rf, uint32_t(ix[e]) * 4u, 0u);
+        double t[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            const bool ok = (e * BLOCK + tid < len) && uint32_t(ix[e]) <= last && isfinite(v[e]) &&
+                            wt[e] > 0.0f;
+            act |= uint64_t(ok) << e;
+            const double wd = ok ? double(wt[e]) : 0.0;
+            const double d = ok ? double(v[e]) - K : 0.0;
+            t[0] += wd;
+            t[1] += wd * d;
+            t[2] += wd * wd;
+            t[3] += ok ? 1.0 : 0.0;
+        }
+        block_sum<4, BLOCK>(t, part, tot);
+        K = (t[3] > 0.5 && t[0] > 0.0) ? K + t[1] / t[0] : 0.0;
+        if (tid == 0) {
+            state[S_W] = t[0];
+            state[S_W2] = t[2];
+            state[S_N] = t[3];
+            state[S_PV] = 0.0;
+        }
+    }
+    // sweep 2: deviations around the first mean (two-pass VV); the weights
+    // are re-read (cache hits) rather than kept in registers
+    {
+        double t[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            const bool ok = (act >> e) & 1u;
+            const float w = buffer_load_f32(rw, tofs, uint32_t(e * BLOCK) * 4u);
+            const double wd = ok ? double(w) : 0.0;
+            const double d = ok ? double(v[e]) - K : 0.0;
+            const double w2 = wd * wd;
+            t[0] += wd * d;
+            t[1] += w2 * d;
+            t[2] += w2 * d * d;
+        }
+        block_sum<3, BLOCK>(t, part, tot);
+        if (tid == 0) {
+            state[S_WD] = t[0];
+            state[S_W2D] = t[1];
+            state[S_W2D2] = t[2];
+            PassCtl c{0.0, 0.0, K, 0, 0, 0, 0};
+            double sv[NSUM];
+            load_state(state, sv);
+            plan(a, sv, c, 0, false);
+            ctl = c;
+        }
+    }
+    __syncthreads();
+
+    // rejection passes
+    for (int k = 0; ctl.go; ++k) {
+        if (ctl.refresh) {
+            // re-accumulate the surviving members around the current mean
+            const double Kn = ctl.mean;
+            double t[NSUM] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) {
+                const bool ok = (act >> e) & 1u;
+                const float w = buffer_load_f32(rw, tofs, uint32_t(e * BLOCK) * 4u);
+                if (ok) add_member(t, double(w), double(v[e]) - Kn, 0.0);
+            }
+            block_sum<NSUM, BLOCK>(t, part, tot);
+            if (tid == 0) {
+                t[S_N] = rint(t[S_N]);
+#pragma unroll
+                for (int q = 0; q < NSUM; ++q) state[q] = t[q];
+                PassCtl c = ctl;
+                c.K = Kn;
+                plan(a, t, c, k, false);
+                ctl = c;
+            }
+            __syncthreads();
+            if (!ctl.go) break;
+        }
+        const double m = ctl.mean, thr = ctl.thr, Kc = ctl.K;
+        uint64_t rem = 0;
+#pragma unroll
+        for (int e = 0; e < EPT; ++e)
+            if (((act >> e) & 1u) && clipped(v[e], m, thr)) rem |= uint64_t(1) << e;
+        act &= ~rem;
+        if (__ballot(rem != 0) != 0) {
+            double r[NSUM] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int e = 0; e < EPT; ++e)
+                if ((rem >> e) & 1u)
+                    add_member(r, double(buffer_load_f32(rw, tofs, uint32_t(e * BLOCK) * 4u)), double(v[e]) - Kc,
+                               0.0);
+#pragma unroll
+            for (int q = 0; q < NSUM; ++q) r[q] = wave_sum(r[q]);
+            if (lane == 0) {
+#pragma unroll
+                for (int q = 0; q < NSUM; ++q) part[q * NW + wid] = r[q];
+            }
+        } else if (lane == 0) {
+#pragma unroll
+            for (int q = 0; q < NSUM; ++q) part[q * NW + wid] = 0.0;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double n_rem = 0.0;
+            for (int q = 0; q < NSUM; ++q) {
+                double x = 0.0;
+                for (int w = 0; w < NW; ++w) x += part[q * NW + w];
+                if (q == S_N) n_rem = x;
+                state[q] -= x;
+            }
+            state[S_N] = rint(state[S_N]);
+            PassCtl c = ctl;
+            after_pass(c, n_rem >= 0.5);
+            if (c.go) {
+                double sv[NSUM];
+                load_state(state, sv);
+                plan(a, sv, c, k + 1, true);
+            }
+            ctl = c;
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        double sv[NSUM];
+        load_state(state, sv);
+        write_profile(a, f, bin, sv, stats_from(sv, ctl.K), ctl.n_iter, ctl.converged);
+    }
+}
+
+// ---------------------------------------------------------------------------
+
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_clip_stream(ClipArgs a) {
+    constexpr int NW = BLOCK / kWave;
+    __shared__ double part[NSUM * NW];
+    __shared__ double tot[NSUM];
+    __shared__ double hist_mean[SS_MAX_ITER];
+    __shared__ double hist_thr[SS_MAX_ITER];
+
+    const int bin = int(blockIdx.x / uint32_t(a.n_frames));
+    const int f = int(blockIdx.x % uint32_t(a.n_frames));
+    const int tid = threadIdx.x;
+    int64_t start, end;
+    row_bounds(a, bin, start, end);
+    const float *__restrict__ fr = a.frames + int64_t(f) * a.n_pix;
+    const bool need_pv = a.model != SS_AZIMUTHAL;
+
+    double K = first_shift(a, fr, start, end);
+    double s1[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t j = start + tid; j < end; j += BLOCK) {
+        const int32_t idx = a.indices[j];
+        const float wt = a.weight[j];
+        const float x = gather(fr, idx, a.n_pix);
+        if (member_ok(x, wt, a.mask, idx)) {
+            const double wd = double(wt);
+            s1[0] += wd;
+            s1[1] += wd * (double(x) - K);
+            s1[2] += wd * wd;
+            s1[3] += 1.0;
+        }
+    }
+    block_sum<4, BLOCK>(s1, part, tot);
+    double s[NSUM] = {s1[0], 0.0, s1[2], 0.0, 0.0, 0.0, s1[3]};
+    K = (s[S_N] > 0.5 && s[S_W] > 0.0) ? K + s1[1] / s[S_W] : 0.0;
+    {
+        double t[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int64_t j = start + tid; j < end; j += BLOCK) {
+            const int32_t idx = a.indices[j];
+            const float wt = a.weight[j];
+            const float x = gather(fr, idx, a.n_pix);
+            if (member_ok(x, wt, a.mask, idx)) {
+                const double wd = double(wt);
+                const double d = double(x) - K;
+                const double w2 = wd * wd;
+                t[0] += wd * d;
+                t[1] += w2 * d;
+                t[2] += w2 * d * d;
+                if (need_pv) t[3] += w2 * poisson_var(x, a.norm ? a.norm[idx] : 1.0f, a.dark_var);
+            }
+        }
+        block_sum<4, BLOCK>(t, part, tot);
+        s[S_WD] = t[0];
+        s[S_W2D] = t[1];
+        s[S_W2D2] = t[2];
+        s[S_PV] = t[3];
+    }
+    // every thread holds the same block-reduced sums and runs the same plan
+    PassCtl c{0.0, 0.0, K, 0, 0, 0, 0};
+    plan(a, s, c, 0, false);
+    for (int k = 0; c.go; ++k) {
+        if (c.refresh) {
+            // re-accumulate the surviving members around the current mean
+            const double Kn = c.mean;
+            double t[NSUM] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+            for (int64_t j = start + tid; j < end; j += BLOCK) {
+                const int32_t idx = a.indices[j];
+                const float wt = a.weight[j];
+                const float x = gather(fr, idx, a.n_pix);
+                if (!member_ok(x, wt, a.mask, idx)) continue;
+                bool alive = true;
+                for (int q = 0; q < k && alive; ++q) alive = !clipped(x, hist_mean[q], hist_thr[q]);
+                if (alive) {
+                    const double pv = need_pv ? poisson_var(x, a.norm ? a.norm[idx] : 1.0f, a.dark_var) : 0.0;
+                    add_member(t, double(wt), double(x) - Kn, pv);
+                }
+            }
+            block_sum<NSUM, BLOCK>(t, part, tot);
+#pragma unroll
+            for (int q = 0; q < NSUM; ++q) s[q] = t[q];
+            s[S_N] = rint(s[S_N]);
+            c.K = Kn;
+            plan(a, s, c, k, false);
+            if (!c.go) break;
+        }
+        if (tid == 0) {
+            hist_mean[k] = c.mean;
+            hist_thr[k] = c.thr;
+        }
+        __syncthreads();
+        double r[NSUM] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        for (int64_t j = start + tid; j < end; j += BLOCK) {
+            const int32_t idx = a.indices[j];
+            const float wt = a.weight[j];
+            const float x = gather(fr, idx, a.n_pix);
+            if (!member_ok(x, wt, a.mask, idx)) continue;
+            bool alive = true;
+            for (int q = 0; q < k && alive; ++q) alive = !clipped(x, hist_mean[q], hist_thr[q]);
+            if (alive && clipped(x, c.mean, c.thr)) {
+                const double pv = need_pv ? poisson_var(x, a.norm ? a.norm[idx] : 1.0f, a.dark_var) : 0.0;
+                add_member(r, double(wt), double(x) - c.K, pv);
+            }
+        }
+        block_sum<NSUM, BLOCK>(r, part, tot);
+#pragma unroll
+        for (int q = 0; q < NSUM; ++q) s[q] -= r[q];
+        s[S_N] = rint(s[S_N]);
+        after_pass(c, r[S_N] >= 0.5);
+        if (c.go) plan(a, s, c, k + 1, true);
+    }
+    if (tid == 0) write_profile(a, f, bin, s, stats_from(s, c.K), c.n_iter, c.converged);
+}
+
+// ---------------------------------------------------------------------------
+
+template <int BLOCK, int EPT>
+void launch_regs(const ClipArgs &a, uint32_t grid, hipStream_t stream) {
+    k_clip_regs<BLOCK, EPT><<<dim3(grid), BLOCK, 0, stream>>>(a);
+}
+
+// Register variant with the smallest footprint that holds the longest row;
+// otherwise the streaming variant.
+void dispatch(const ClipArgs &a, int32_t max_row, uint32_t grid, hipStream_t stream) {
+    const bool regs = a.model == SS_AZIMUTHAL && a.mask == nullptr && a.n_pix < (int64_t(1) << 30);
+    if (regs && max_row <= 256 * 4) launch_regs<256, 4>(a, grid, stream);
+    else if (regs && max_row <= 256 * 8) launch_regs<256, 8>(a, grid, stream);
+    else if (regs && max_row <= 256 * 16) launch_regs<256, 16>(a, grid, stream);
+    else if (regs && max_row <= 512 * 16) launch_regs<512, 16>(a, grid, stream);
+    else if (regs && max_row <= 512 * 24) launch_regs<512, 24>(a, grid, stream);
+    else if (regs && max_row <= 512 * 32) launch_regs<512, 32>(a, grid, stream);
+    else if (regs && max_row <= 512 * 40) launch_regs<512, 40>(a, grid, stream);
+    else if (regs && max_row <= 1024 * 24) launch_regs<1024, 24>(a, grid, stream);
+    else if (max_row <= 4096) k_clip_stream<256><<<dim3(grid), 256, 0, stream>>>(a);
+    else k_clip_stream<1024><<<dim3(grid), 1024, 0, stream>>>(a);
+}
+
+}  // namespace
+}  // namespace ss
+
+static int clip_entry(const float *frames, const float *norm, const uint8_t *mask, int32_t n_frames,
+                      const ss_csr *csr, const ss_params *p, const ss_profile *out, bool integrate_only,
+                      hipStream_t stream) {
+    if (!csr || !p || !out) return SS_EINVAL;
+    if (n_frames < 0) return SS_ESIZE;
+    if (csr->n_bins <= 0 || csr->n_bins > SS_MAX_BINS || csr->n_pix < 0 ||
+        csr->n_pix >= (int64_t(1) << 31) || csr->nnz < 0 || csr->nnz >= (int64_t(1) << 31) ||
+        csr->max_row < 0)
+        return SS_ESIZE;
+    if (!integrate_only && (p->max_iter < 0 || p->max_iter > SS_MAX_ITER)) return SS_ESIZE;
+    if (p->error_model != SS_AZIMUTHAL && p->error_model != SS_POISSON && p->error_model != SS_HYBRID)
+        return SS_EINVAL;
+    if (n_frames == 0) return SS_OK;
+    if (csr->n_pix == 0 && csr->nnz > 0) return SS_ESIZE;
+    if (!frames || !csr->indptr || (csr->nnz > 0 && (!csr->indices || !csr->weight)) || !out->mean ||
+        !out->std || !out->sem || !out->sum_w || !out->n_members || !out->n_iter || !out->converged)
+        return SS_EINVAL;
+    const int64_t grid = int64_t(csr->n_bins) * n_frames;
+    if (grid >= (int64_t(1) << 31)) return SS_ESIZE;
+    ss::ClipArgs a;
+    a.frames = frames;
+    a.n_pix = csr->n_pix;
+    a.norm = norm;
+    a.mask = mask;
+    a.n_frames = n_frames;
+    a.n_bins = csr->n_bins;
+    a.indptr = csr->indptr;
+    a.indices = csr->indices;
+    a.weight = csr->weight;
+    a.nnz = csr->nnz;
+    a.cutoff = double(p->cutoff);
+    a.max_iter = integrate_only ? 0 : p->max_iter;
+    a.model = p->error_model;
+    a.dark_var = double(p->dark_var);
+    a.mean = out->mean;
+    a.std = out->std;
+    a.sem = out->sem;
+    a.sum_w = out->sum_w;
+    a.n_members = out->n_members;
+    a.n_iter = out->n_iter;
+    a.converged = out->converged;
+    ss::dispatch(a, csr->max_row, uint32_t(grid), stream);
+    SS_RETURN_IF_LAUNCH_FAILED();
+    return SS_OK;
+}
+
+extern "C" int ss_sigma_clip(const float *frames, const float *norm, const uint8_t *mask,
+                             int32_t n_frames, const ss_csr *csr, const ss_params *params,
+                             const ss_profile *out, hipStream_t stream) {
+    return clip_entry(frames, norm, mask, n_frames, csr, params, out, false, stream);
+}
+
+extern "C" int ss_integrate(const float *frames, const float *norm, const uint8_t *mask,
+                            int32_t n_frames, const ss_csr *csr, const ss_params *params,
+                            const ss_profile *out, hipStream_t stream) {
+    return clip_entry(frames, norm, mask, n_frames, csr, params, out, true, stream);
+}

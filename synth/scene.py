@@ -249,9 +249,8 @@ def jungfrau_frame(geom: Geometry, frame_idx: int):
     for g in (0, 1):
         sat = (level == g) & (ped[g] + e * gain[g] > ADC_MAX)
         level[sat] = g + 1
-    idx = np.arange(e.size)
-    p = ped[level, idx].astype(np.float64)
-    k = gain[level, idx].astype(np.float64)
+    p = np.where(level == 0, ped[0], np.where(level == 1, ped[1], ped[2])).astype(np.float64)
+    k = np.where(level == 0, gain[0], np.where(level == 1, gain[1], gain[2])).astype(np.float64)
     adc = np.clip(np.rint(p + e * k + rng.normal(0.0, 2.0, e.size)), 0, ADC_MAX).astype(np.uint16)
     code = np.asarray(GAIN_LEVEL_CODES, dtype=np.uint16)[level]
     word = (code << np.uint16(14)) | adc

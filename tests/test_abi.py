@@ -1,0 +1,142 @@
+"""C-ABI library checks that need no GPU: exported symbols, the host-side
+geometry builder against the oracle's independent one, and argument errors
+detected before any launch."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import geometry as G
+from paper_2411_09515_amd import binding as B
+from paper_2411_09515_amd import api
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "sigsep.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^(?:int|size_t|const char \*)\s*(ss_\w+)\s*\(", text, re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = _declared()
+    assert len(names) == len(B.EXPORTED) and set(names) == set(B.EXPORTED)
+    L = B.lib()
+    for n in names:
+        assert getattr(L, n) is not None
+    assert L.ss_version() >= 100
+    assert B.strerror(B.SS_OK) == "ok" and B.strerror(B.SS_EINVAL) == "invalid argument"
+
+
+def _compare_csr(host, ref, norm=None):
+    assert host["nnz"] == ref.nnz
+    assert np.array_equal(host["indptr"], ref.indptr)
+    assert np.array_equal(host["indices"].astype(np.int64), ref.indices)
+    want = ref.coef * (1.0 if norm is None else norm.reshape(-1).astype(np.float64)[ref.indices])
+    assert np.allclose(host["weight"], want, rtol=1e-6, atol=0)
+    assert host["max_row"] == int(np.diff(ref.indptr).max())
+    assert host["tth_max"] == pytest.approx(ref.tth_max, rel=1e-13)
+
+
+def test_host_csr_matches_oracle_no_split():
+    g = synth.SMALL
+    m = synth.stripe_mask(g)
+    host = api.build_csr_host(g.height, g.width, g.pixel_m, g.dist_m, g.centre_row, g.centre_col,
+                              g.n_bins, "none", m)
+    _compare_csr(host, G.csr_for(g, m))
+
+
+def test_host_csr_matches_oracle_bbox_with_norm():
+    g = synth.JUNGFRAU1M
+    m = synth.stripe_mask(g)
+    norm = synth.normalisation(g)
+    host = api.build_csr_host(g.height, g.width, g.pixel_m, g.dist_m, g.centre_row, g.centre_col,
+                              g.n_bins, "bbox", m, norm)
+    _compare_csr(host, G.csr_for(g, m), norm)
+
+
+def test_radial_coords_decode_to_oracle_angles():
+    g = synth.JUNGFRAU1M
+    m = synth.stripe_mask(g).reshape(-1)
+    host = api.build_csr_host(g.height, g.width, g.pixel_m, g.dist_m, g.centre_row, g.centre_col,
+                              g.n_bins, "bbox", m)
+    rc = host["rcoord"]
+    assert np.all(rc[m != 0] == B.SS_RC_MASKED)
+    ok = m == 0
+    t = (rc[ok] >> B.SS_RC_FRAC_BITS).astype(np.int64) - 1
+    frac = (rc[ok] & ((1 << B.SS_RC_FRAC_BITS) - 1)) / float(1 << B.SS_RC_FRAC_BITS)
+    pos = G.position_for(g)[ok]
+    w = host["width"]
+    assert host["centre0"] == pytest.approx(w / 2, rel=1e-14)
+    inner = (t >= 0) & (t <= g.n_bins - 2)
+    decoded = host["centre0"] + (t[inner] + frac[inner]) * w
+    assert np.abs(decoded - pos[inner]).max() <= 2.0 ** -B.SS_RC_FRAC_BITS * w * 1.01
+    # outside the centre range the interval index is clamped
+    assert np.all(pos[t == -1] < host["centre0"] + 1e-12)
+    assert np.all(pos[t == g.n_bins - 1] >= host["centre0"] + (g.n_bins - 1) * w - 1e-12)
+
+
+def test_host_builder_argument_errors():
+    L = B.lib()
+    nnz, mr, tm = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_double()
+    r = L.ss_build_csr(10, 10, 75e-6, 0.1, 5.0, 5.0, 10, 7, None, None, None, None, None, 0,
+                       ctypes.byref(nnz), ctypes.byref(mr), ctypes.byref(tm))
+    assert r == B.SS_EINVAL
+    r = L.ss_build_csr(10, 10, 75e-6, 0.1, 5.0, 5.0, B.SS_MAX_BINS + 1, 0, None, None, None, None, None, 0,
+                       ctypes.byref(nnz), ctypes.byref(mr), ctypes.byref(tm))
+    assert r == B.SS_ESIZE
+    r = L.ss_build_csr(0, 10, 75e-6, 0.1, 5.0, 5.0, 10, 0, None, None, None, None, None, 0,
+                       ctypes.byref(nnz), ctypes.byref(mr), ctypes.byref(tm))
+    assert r == B.SS_ESIZE
+    r = L.ss_build_csr(10, 10, 75e-6, 0.1, 5.0, 5.0, 10, 0, None, None, None, None, None, 0,
+                       ctypes.byref(nnz), ctypes.byref(mr), ctypes.byref(tm))
+    assert r == B.SS_OK and nnz.value == 100
+    ip = np.zeros(11, dtype=np.int64)
+    ix = np.zeros(10, dtype=np.int32)
+    wt = np.zeros(10, dtype=np.float32)
+    r = L.ss_build_csr(10, 10, 75e-6, 0.1, 5.0, 5.0, 10, 0, None, None, ip.ctypes.data, ix.ctypes.data,
+                       wt.ctypes.data, 10, ctypes.byref(nnz), ctypes.byref(mr), ctypes.byref(tm))
+    assert r == B.SS_ESIZE  # capacity 10 < nnz 100
+
+
+def test_device_calls_reject_bad_arguments_before_launch():
+    """Host-side validation returns before anything reaches the HIP runtime."""
+    L = B.lib()
+    fake = ctypes.c_void_p(4096)
+    assert L.ss_correct(None, 1, 16, fake, fake, None, fake, None, None) == B.SS_EINVAL
+    assert L.ss_correct(fake, -1, 16, fake, fake, None, fake, None, None) == B.SS_ESIZE
+    assert L.ss_correct(fake, 1, 1 << 31, fake, fake, None, fake, None, None) == B.SS_ESIZE
+    assert L.ss_correct(fake, 0, 16, fake, fake, None, fake, None, None) == B.SS_OK
+    csr = B.Csr(10, 5, 100, 50, 4096, 4096, 4096)
+    prof = B.Profile(*([4096] * 7))
+    good = B.Params(3.0, 5, 0, 0.0, 3.0, 0.0, 3.0, 3, 3)
+    bad_iter = B.Params(3.0, B.SS_MAX_ITER + 1, 0, 0.0, 3.0, 0.0, 3.0, 3, 3)
+    bad_model = B.Params(3.0, 5, 7, 0.0, 3.0, 0.0, 3.0, 3, 3)
+    ref = ctypes.byref
+    assert L.ss_sigma_clip(fake, None, None, 1, ref(csr), ref(bad_iter), ref(prof), None) == B.SS_ESIZE
+    assert L.ss_sigma_clip(fake, None, None, 1, ref(csr), ref(bad_model), ref(prof), None) == B.SS_EINVAL
+    assert L.ss_sigma_clip(None, None, None, 1, ref(csr), ref(good), ref(prof), None) == B.SS_EINVAL
+    assert L.ss_sigma_clip(fake, None, None, 0, ref(csr), ref(good), ref(prof), None) == B.SS_OK
+    big = B.Csr(B.SS_MAX_BINS + 1, 5, 100, 50, 4096, 4096, 4096)
+    assert L.ss_sigma_clip(fake, None, None, 1, ref(big), ref(good), ref(prof), None) == B.SS_ESIZE
+    # integrate ignores max_iter
+    assert L.ss_integrate(fake, None, None, 0, ref(csr), ref(bad_iter), ref(prof), None) == B.SS_OK
+
+    rad = B.Radial(10, 0.05, 0.1, 4096)
+    need = L.ss_classify_workspace(2, 100, 10)
+    assert need > 0
+    even = B.Params(3.0, 5, 0, 0.0, 3.0, 0.0, 3.0, 4, 3)
+    args = (fake, None, 2, 10, 10, ref(rad), ref(prof))
+    assert L.ss_classify(*args, ref(even), fake, fake, 8, fake, None, 0, None, fake, need, None) == B.SS_EINVAL
+    assert L.ss_classify(*args, ref(good), fake, fake, 8, fake, None, 0, None, fake, need - 1,
+                         None) == B.SS_ESIZE
+    assert L.ss_classify(*args, ref(good), fake, None, 8, fake, None, 0, None, fake, need,
+                         None) == B.SS_EINVAL
+    assert L.ss_classify(*args, ref(good), fake, fake, -1, fake, None, 0, None, fake, need,
+                         None) == B.SS_ESIZE
+    assert L.ss_compress(*args, ref(good), None, fake, 8, fake, fake, need, None) == B.SS_EINVAL
+    assert L.ss_peakfind(*args, ref(good), None, 8, fake, fake, need, None) == B.SS_EINVAL

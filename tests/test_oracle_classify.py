@@ -58,7 +58,7 @@ def test_kept_fraction_follows_normal_tails(golden):
     prof = S.integrate(values, None, csr)
     pos = np.full(n_pix, csr.centres[0])
     for n, key in ((1, "tail_n1_percent"), (2, "tail_n2_percent"), (3, "tail_n3_percent")):
-        idx, _ = K.compress(values, None, None, pos, csr.centres, prof, n_pick=float(n))
+        idx, _ = K.compress(values, None, pos, csr.centres, prof, n_pick=float(n))
         frac = idx.size / n_pix
         p = 1.0 - ndtr(n)
         assert abs(frac - p) <= 5 * math.sqrt(p * (1 - p) / n_pix)
@@ -80,7 +80,7 @@ def test_round_trip_invariant():
     g, m, csr, f, prof, _ = _small_frame(1)
     pos = G.position_for(g)
     n_pick = 3.0
-    idx, val = K.compress(f, None, m, pos, csr.centres, prof, n_pick=n_pick)
+    idx, val = K.compress(f, m, pos, csr.centres, prof, n_pick=n_pick)
     assert np.all(np.diff(idx) > 0)
     dense = K.densify(idx, val, g.n_pix, m, pos, csr.centres, prof)
     v = f.reshape(-1).astype(np.float64)
@@ -93,7 +93,7 @@ def test_round_trip_invariant():
     assert np.all(v[drop] - dense[drop] <= n_pick * sd[drop])
     assert np.all(dense[~valid] == 0.0)
     # raising the threshold never keeps more
-    idx2, _ = K.compress(f, None, m, pos, csr.centres, prof, n_pick=4.0)
+    idx2, _ = K.compress(f, m, pos, csr.centres, prof, n_pick=4.0)
     assert set(idx2.tolist()) <= set(idx.tolist())
 
 
@@ -123,14 +123,14 @@ def _peaks_scipy(v, valid, cand, mu, se, H, W, patch, min_count):
 def test_peakfind_three_implementations_agree(patch, min_count):
     g, m, csr, f, prof, _ = _small_frame(2)
     pos = G.position_for(g)
-    args = (f, None, m, g.height, g.width, pos, csr.centres, prof)
+    args = (f, m, g.height, g.width, pos, csr.centres, prof)
     a = K.peakfind(*args, snr=3.0, patch=patch, min_count=min_count)
     b = K.peakfind_loops(*args, snr=3.0, patch=patch, min_count=min_count)
     assert a.size > 5
     assert np.array_equal(a["index"], b["index"])
     for k in ("y", "x", "intensity", "sigma"):
         assert np.allclose(a[k], b[k], rtol=1e-12)
-    v, mu, se, valid = K.pixel_state(f, None, m, pos, csr.centres, prof)
+    v, mu, se, valid = K.pixel_state(f, m, pos, csr.centres, prof)
     cand = valid & (v - mu >= 3.0 * se)
     sel, y, x, I, s = _peaks_scipy(v, valid, cand, mu, se, g.height, g.width, patch, min_count)
     assert np.array_equal(a["index"], sel)
@@ -144,7 +144,7 @@ def test_peakfind_tie_goes_to_lower_index():
     v[[6, 7, 11]] = 10.0  # three equal pixels: (1, 1), (1, 2), (2, 1)
     prof = dict(n_members=np.array([1]), mean=np.array([0.0]), std=np.array([1.0]))
     pos = np.zeros(H * W)
-    out = K.peakfind(v, None, None, H, W, pos, np.array([0.0]), prof, snr=3.0, patch=3, min_count=3)
+    out = K.peakfind(v, None, H, W, pos, np.array([0.0]), prof, snr=3.0, patch=3, min_count=3)
     assert out["index"].tolist() == [6]
     assert out["intensity"][0] == 30.0
     assert out["y"][0] == pytest.approx(5.5 / 3) and out["x"][0] == pytest.approx(5.5 / 3)
@@ -167,7 +167,7 @@ def test_isolated_spots_are_found_once():
     prof = S.sigma_clip(img, None, csr)
     pos = G.centre_angle(H, W, 75e-6, 0.1, 100.3, 100.7)
     # the setting of the paper's comparison (Sec. 4.1): SNR 3, 4 pixels in a 5x5 patch
-    pk = K.peakfind(img, None, None, H, W, pos, csr.centres, prof, snr=3.0, patch=5, min_count=4)
+    pk = K.peakfind(img, None, H, W, pos, csr.centres, prof, snr=3.0, patch=5, min_count=4)
     strong = [p for p in pk if p["intensity"] > 1000]
     assert len(strong) == len(centres)
     for cy, cx in centres:

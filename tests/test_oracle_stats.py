@@ -154,7 +154,7 @@ def test_weighted_mean_is_ratio_of_sums(rng):
     signal = rng.uniform(10, 100, n)
     norm = rng.uniform(0.3, 1.0, n)
     c = rng.uniform(0.05, 1.0, n)
-    out = S.integrate(signal, norm, _OneRowCsr(c))
+    out = S.integrate(signal / norm, norm, _OneRowCsr(c))
     assert out["mean"][0] == pytest.approx(np.dot(c, signal) / np.dot(c, norm), rel=1e-13)
     assert out["sum_w"][0] == pytest.approx(np.dot(c, norm), rel=1e-13)
 
@@ -166,7 +166,7 @@ def test_flat_image_any_split():
         csr = G.build_csr(H, W, 75e-6, 0.003, 19.2, 20.7, 30, split)
         norm = np.linspace(0.5, 1.0, H * W)
         k = 37.25
-        out = S.integrate(k * norm, norm, csr)
+        out = S.integrate((k * norm) / norm, norm, csr)
         ne = out["n_members"] > 0
         assert ne.all()
         assert np.allclose(out["mean"][ne], k, rtol=1e-14)
