@@ -101,6 +101,8 @@ def main():
     ap.add_argument("--latency-iters", type=int, default=200)
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one plain 1 GiB device copy (a known-size reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (frames shard across GPUs "
@@ -163,6 +165,14 @@ def main():
     achieved = alg[dom] / (stage[dom] * 1e-3) / 1e9
     print(f"# stages ms: {stage}; kept {n_kept}, peaks {n_peaks}", file=sys.stderr, flush=True)
 
+    if args.copy_calibration:
+        src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
     # single-frame latency: one raw frame through the whole path, per call
     one = api.Pipeline(geo, params, 1, pipe.pedestal, pipe.gain, kept_capacity=1 << 16, peak_capacity=1 << 12,
                        device=dev)
@@ -175,7 +185,7 @@ def main():
         b.synchronize()
         if i >= 5:
             lat.append(a.elapsed_time(b))
-    lat = np.array(lat)
+    lat = np.array(lat if lat else [float("nan")])
 
     line = {
         "metric": METRIC,

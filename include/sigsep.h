@@ -58,6 +58,7 @@ extern "C" {
 #define SS_MAX_BINS 4094
 #define SS_MAX_ITER 32
 #define SS_MAX_PATCH 15
+#define SS_N_CLASSES 7
 
 /*
  * Pixel-to-bin matrix in CSR form (rows = radial bins), Sec. 2.2: the
@@ -65,15 +66,22 @@ extern "C" {
  * per-entry weight omega = c[i, r] * norm_i of eq. omega (the pixel's share
  * of the bin times its normalisation factor).  Row entries have ascending
  * pixel indices.  max_row is the length of the longest row.
+ *
+ * Optional schedule (from ss_csr_schedule): bin_order lists the bins grouped
+ * by row-length class, longest class first, and class_count[c] is the number
+ * of bins in class c; the clip then launches one work-group size per class.
+ * With bin_order == NULL one work-group size fits the longest row.
  */
 typedef struct {
     int32_t n_bins;
     int32_t max_row;
     int64_t n_pix;
     int64_t nnz;
-    const int64_t *indptr;  /* [dev] [n_bins + 1] */
-    const int32_t *indices; /* [dev] [nnz]        */
-    const float *weight;    /* [dev] [nnz]        */
+    const int64_t *indptr;    /* [dev] [n_bins + 1]   */
+    const int32_t *indices;   /* [dev] [nnz]          */
+    const float *weight;      /* [dev] [nnz]          */
+    const int32_t *bin_order; /* [dev] [n_bins] or NULL */
+    int32_t class_count[SS_N_CLASSES];
 } ss_csr;
 
 /*
@@ -172,6 +180,19 @@ int ss_build_csr(int32_t height, int32_t width, double pixel_m, double dist_m,
                  const uint8_t *mask, const float *norm,
                  int64_t *indptr, int32_t *indices, float *weight, int64_t capacity,
                  int64_t *nnz, int32_t *max_row, double *tth_max);
+
+/*
+ * ss_csr_schedule [host] -- group the bins of a CSR by row length for
+ * ss_sigma_clip.  Class c holds the rows of at most ss_class_rows(c) entries
+ * not held by a smaller class (the last class: any length); bin_order [host]
+ * [n_bins] receives the bins of the longest class first, each class in bin
+ * order; class_count [host] [SS_N_CLASSES] the class sizes.
+ * Errors: SS_EINVAL, SS_ESIZE.
+ */
+int ss_csr_schedule(const int64_t *indptr, int32_t n_bins, int32_t *bin_order, int32_t *class_count);
+
+/* Largest row length of class c (0 <= c < SS_N_CLASSES - 1). */
+int32_t ss_class_rows(int32_t c);
 
 /*
  * ss_radial_coords [host] -- rcoord [host] [n_pix] of the pixel-centre

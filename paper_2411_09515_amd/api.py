@@ -74,13 +74,17 @@ def build_csr_host(height, width, pixel_m, dist_m, centre_row, centre_col, n_bin
     B.check("ss_build_csr", L.ss_build_csr(*args, _host_ptr(indptr), _host_ptr(indices), _host_ptr(weight),
                                            nnz.value, ctypes.byref(nnz), ctypes.byref(max_row),
                                            ctypes.byref(tmax)))
+    order = np.zeros(n_bins, dtype=np.int32)
+    counts = np.zeros(B.SS_N_CLASSES, dtype=np.int32)
+    B.check("ss_csr_schedule", L.ss_csr_schedule(_host_ptr(indptr), n_bins, _host_ptr(order), _host_ptr(counts)))
     rc = np.zeros(height * width, dtype=np.uint32)
     c0, w = ctypes.c_double(), ctypes.c_double()
     B.check("ss_radial_coords", L.ss_radial_coords(height, width, pixel_m, dist_m, centre_row, centre_col,
                                                    n_bins, tmax.value, _host_ptr(mask), _host_ptr(rc),
                                                    ctypes.byref(c0), ctypes.byref(w)))
     return dict(indptr=indptr, indices=indices[: nnz.value], weight=weight[: nnz.value], nnz=nnz.value,
-                max_row=max_row.value, tth_max=tmax.value, rcoord=rc, centre0=c0.value, width=w.value)
+                max_row=max_row.value, tth_max=tmax.value, rcoord=rc, centre0=c0.value, width=w.value,
+                bin_order=order, class_count=counts)
 
 
 class Geometry:
@@ -99,6 +103,9 @@ class Geometry:
         self.indices = torch.from_numpy(np.ascontiguousarray(h["indices"])).to(dev)
         self.weight = torch.from_numpy(np.ascontiguousarray(h["weight"])).to(dev)
         self.rcoord = torch.from_numpy(h["rcoord"].view(np.int32)).to(dev)
+        self.bin_order = torch.from_numpy(h["bin_order"]).to(dev)
+        self.class_count = h["class_count"]
+        self.scheduled = True
         self.norm = None if norm is None else torch.from_numpy(
             np.array(norm, dtype=np.float32).reshape(-1)).to(dev)
         self.mask = None if mask is None else torch.from_numpy(
@@ -112,8 +119,11 @@ class Geometry:
                    geom.n_bins, geom.split, mask, norm, device)
 
     def csr(self) -> B.Csr:
+        """The C struct; with ``scheduled`` the clip launches per row-length class."""
+        counts = (ctypes.c_int32 * B.SS_N_CLASSES)(*[int(c) for c in self.class_count])
         return B.Csr(self.n_bins, self.max_row, self.n_pix, self.nnz, self.indptr.data_ptr(),
-                     self.indices.data_ptr(), self.weight.data_ptr())
+                     self.indices.data_ptr(), self.weight.data_ptr(),
+                     self.bin_order.data_ptr() if self.scheduled else None, counts)
 
     def radial(self) -> B.Radial:
         return B.Radial(self.n_bins, self.centre0, self.bin_width, self.rcoord.data_ptr())

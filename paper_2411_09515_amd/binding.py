@@ -22,9 +22,11 @@ SS_RC_MASKED = 0xFFFFFFFF
 SS_MAX_BINS = 4094
 SS_MAX_ITER = 32
 SS_MAX_PATCH = 15
+SS_N_CLASSES = 7
 
 EXPORTED = (
-    "ss_strerror", "ss_version", "ss_build_csr", "ss_radial_coords", "ss_correct",
+    "ss_strerror", "ss_version", "ss_build_csr", "ss_csr_schedule", "ss_class_rows", "ss_radial_coords",
+    "ss_correct",
     "ss_integrate", "ss_sigma_clip", "ss_classify_workspace", "ss_classify",
     "ss_compress", "ss_peakfind",
 )
@@ -39,7 +41,8 @@ class SigsepError(RuntimeError):
 class Csr(ctypes.Structure):
     _fields_ = [("n_bins", ctypes.c_int32), ("max_row", ctypes.c_int32), ("n_pix", ctypes.c_int64),
                 ("nnz", ctypes.c_int64), ("indptr", ctypes.c_void_p), ("indices", ctypes.c_void_p),
-                ("weight", ctypes.c_void_p)]
+                ("weight", ctypes.c_void_p), ("bin_order", ctypes.c_void_p),
+                ("class_count", ctypes.c_int32 * SS_N_CLASSES)]
 
 
 class Params(ctypes.Structure):
@@ -85,6 +88,10 @@ def lib():
         L.ss_build_csr.restype = ctypes.c_int
         L.ss_build_csr.argtypes = [i32, i32, f64, f64, f64, f64, i32, i32, vp, vp, vp, vp, vp, i64,
                                    P(i64), P(i32), P(f64)]
+        L.ss_csr_schedule.restype = ctypes.c_int
+        L.ss_csr_schedule.argtypes = [vp, i32, vp, vp]
+        L.ss_class_rows.restype = ctypes.c_int32
+        L.ss_class_rows.argtypes = [i32]
         L.ss_radial_coords.restype = ctypes.c_int
         L.ss_radial_coords.argtypes = [i32, i32, f64, f64, f64, f64, i32, f64, vp, vp, P(f64), P(f64)]
         L.ss_correct.restype = ctypes.c_int

@@ -5,16 +5,18 @@
 // lookup table over the n_bins + 1 intervals between bin centres: for each
 // interval the bracketing non-empty bins and their mean/std, so that the
 // background of a pixel is one table read plus a linear interpolation.  It
-// also clears the look-back flags, the tile counter and the output counts.
+// also clears the output counts.
 //
-// k_classify works on tiles of TILE consecutive pixels of one frame.  A tile
-// classifies its pixels, runs the peak test for the (rare) candidates by
-// reading their patch directly, and then appends its kept pixels and peaks
-// in index order.  Ordering across tiles is a decoupled look-back: each tile
-// publishes its counts, then adds up its predecessors' counts until it meets
-// one that published an inclusive prefix.  Tiles take their id from an
-// atomic counter, so a tile only ever waits on tiles whose work-groups are
-// already running, and every wait ends.
+// k_pixel_state stages 2-D tiles of pixels (plus a halo of half a patch) in
+// LDS and computes, once per pixel and frame, four bits: valid, kept
+// (v - mu > n_pick sigma_eff), peak candidate (v - mu >= snr sigma_eff) and
+// peak (the patch test of the peak finder, evaluated from LDS).
+//
+// Ordered output without atomics: tiles of kTile consecutive pixels of one
+// frame count their kept pixels and peaks (k_tile_counts), one work-group
+// per frame turns the counts into exclusive offsets (k_tile_scan), and the
+// tiles write their entries in pixel order at those offsets (k_tile_write),
+// computing peak records on the way.
 
 #include <cmath>
 
@@ -24,43 +26,57 @@ namespace ss {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kPPT = 16;
+constexpr int kPPT = 32;  // consecutive pixels per thread
 constexpr int kTile = kBlock * kPPT;
 constexpr int kNW = kBlock / kWave;
 constexpr int kTableBlock = 256;
 
-constexpr uint64_t kAggregate = uint64_t(1) << 62;
-constexpr uint64_t kPrefix = uint64_t(2) << 62;
-constexpr uint64_t kCountMask = kAggregate - 1;
-constexpr int kPeakShift = 31;
+constexpr int kScanBlock = 1024;
 
 struct Seg {
     double m_lo, dm, s_lo, ds, inv_span;
     int32_t lo, pad;
 };
 
-struct Workspace {
-    uint32_t *counter;
-    uint64_t *flags;  // [n_frames][tiles]
-    Seg *table;       // [n_frames][n_bins + 1]
+// The same interpolation segment in float32 for the fast path.
+struct SegF {
+    float m_lo, dm, s_lo, ds, inv_span;
+    int32_t lo;
 };
+
+struct Workspace {
+    SegF *tablef;       // [n_frames][n_bins + 1]
+    uint32_t *counts;   // per tile: kept | peaks << 16, [n_frames][tiles]
+    uint64_t *offsets;  // per tile: kept offset | peak offset << 32, [n_frames][tiles]
+    Seg *table;         // [n_frames][n_bins + 1]
+    uint8_t *bits;      // pixel state [n_frames][n_pix]
+};
+
+constexpr uint8_t kValid = 1, kKeep = 2, kCand = 4, kPeak = 8;
 
 size_t tiles_of(int64_t n_pix) { return size_t((n_pix + kTile - 1) / kTile); }
 
+size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
+
 size_t workspace_bytes(int32_t n_frames, int64_t n_pix, int32_t n_bins) {
-    return 256 + size_t(n_frames) * tiles_of(n_pix) * sizeof(uint64_t) +
-           size_t(n_frames) * size_t(n_bins + 1) * sizeof(Seg) + 256;
+    const size_t tiles = size_t(n_frames) * tiles_of(n_pix);
+    return 256 + align256(size_t(n_frames) * size_t(n_bins + 1) * sizeof(SegF)) + align256(tiles * sizeof(uint32_t)) + align256(tiles * sizeof(uint64_t)) +
+           align256(size_t(n_frames) * size_t(n_bins + 1) * sizeof(Seg)) + align256(size_t(n_frames) * size_t(n_pix));
 }
 
-Workspace carve(void *base, int32_t n_frames, int64_t n_pix) {
-    char *p = static_cast<char *>(base);
+Workspace carve(void *base, int32_t n_frames, int64_t n_pix, int32_t n_bins) {
+    const size_t tiles = size_t(n_frames) * tiles_of(n_pix);
+    uintptr_t p = (reinterpret_cast<uintptr_t>(base) + 255) & ~uintptr_t(255);
     Workspace w;
-    w.counter = reinterpret_cast<uint32_t *>(p);
-    p += 256;
-    w.flags = reinterpret_cast<uint64_t *>(p);
-    p += size_t(n_frames) * tiles_of(n_pix) * sizeof(uint64_t);
-    uintptr_t q = (reinterpret_cast<uintptr_t>(p) + 255) & ~uintptr_t(255);
-    w.table = reinterpret_cast<Seg *>(q);
+    w.tablef = reinterpret_cast<SegF *>(p);
+    p += align256(size_t(n_frames) * size_t(n_bins + 1) * sizeof(SegF));
+    w.counts = reinterpret_cast<uint32_t *>(p);
+    p += align256(tiles * sizeof(uint32_t));
+    w.offsets = reinterpret_cast<uint64_t *>(p);
+    p += align256(tiles * sizeof(uint64_t));
+    w.table = reinterpret_cast<Seg *>(p);
+    p += align256(size_t(n_frames) * size_t(n_bins + 1) * sizeof(Seg));
+    w.bits = reinterpret_cast<uint8_t *>(p);
     return w;
 }
 
@@ -137,13 +153,12 @@ __global__ __launch_bounds__(kTableBlock) void k_profile_table(
             s.s_lo = sf[b];
         }
         tab[t1] = s;
+        ws.tablef[int64_t(f) * (n_bins + 1) + t1] =
+            SegF{float(s.m_lo), float(s.dm), float(s.s_lo), float(s.ds), float(s.inv_span), s.lo};
     }
-    uint64_t *fl = ws.flags + int64_t(f) * tiles;
-    for (int i = tid; i < tiles; i += kTableBlock) fl[i] = 0;
     if (tid == 0) {
         if (n_kept) n_kept[f] = 0;
         if (n_peaks) n_peaks[f] = 0;
-        if (f == 0) *ws.counter = 0;
     }
 }
 
@@ -151,6 +166,7 @@ __global__ __launch_bounds__(kTableBlock) void k_profile_table(
 
 struct ClassArgs {
     const float *frames;
+    int32_t n_frames;
     const uint8_t *mask;
     const uint32_t *rcoord;
     int64_t n_pix;
@@ -180,197 +196,425 @@ __device__ inline void background(uint32_t rc, const Seg *__restrict__ tab, int 
     se = sqrt(sd * sd + noise2);
 }
 
-__device__ inline bool pixel_valid(float x, uint32_t rc, const uint8_t *mask, int64_t i) {
-    return rc != SS_RC_MASKED && isfinite(x) && !(mask && mask[i]);
+
+// ---- per-pixel state and peak test ---------------------------------------------------
+
+__device__ inline uint8_t pixel_bits(float x, uint32_t rc, bool masked, const Seg *__restrict__ tab, int n_bins,
+                                     double noise2, double n_pick, double snr) {
+    if (rc == SS_RC_MASKED || masked || !isfinite(x)) return 0;
+    double mu, se;
+    background(rc, tab, n_bins, noise2, mu, se);
+    const double d = double(x) - mu;
+    return kValid | (d > n_pick * se ? kKeep : 0) | (d >= snr * se ? kCand : 0);
 }
+
+// Float32 version of pixel_bits.  Its rounding errors are below 1e-6 of the
+// scale |v| + |mu| + sigma terms, so when v - mu is further than 1e-5 of that
+// scale from both thresholds its decisions are those of the float64
+// computation; otherwise the pixel is decided again in float64.
+__device__ inline uint8_t pixel_bits_fast(float x, uint32_t rc, const SegF &sg, const Seg *__restrict__ tab,
+                                          int n_bins, float noise2f, double noise2, float n_pick_f, float snr_f,
+                                          double n_pick, double snr) {
+    if (rc == SS_RC_MASKED || !isfinite(x)) return 0;
+    const int t1 = min(int(rc >> SS_RC_FRAC_BITS), n_bins);
+    const float frac = float(rc & ((1u << SS_RC_FRAC_BITS) - 1u)) * (1.0f / float(1u << SS_RC_FRAC_BITS));
+    const float u = (float(t1 - 1 - sg.lo) + frac) * sg.inv_span;
+    const float mu = fmaf(sg.dm, u, sg.m_lo);
+    const float sd = fmaf(sg.ds, u, sg.s_lo);
+    const float se = noise2f == 0.0f ? fabsf(sd) : sqrtf(fmaf(sd, sd, noise2f));
+    const float d = x - mu;
+    const float tk = n_pick_f * se, tc = snr_f * se;
+    const float tol = 1e-5f * (fabsf(x) + fabsf(sg.m_lo) + fabsf(sg.dm) + fabsf(sg.s_lo) + fabsf(sg.ds) + se) +
+                      1e-30f;
+    if (fabsf(d - tk) <= tol || fabsf(d - tc) <= tol)
+        return pixel_bits(x, rc, false, tab, n_bins, noise2, n_pick, snr);
+    return kValid | (d > tk ? kKeep : 0) | (d >= tc ? kCand : 0);
+}
+
+// 2-D stencil tile (core pixels), work-group size and frames per
+// work-group; compile-time tunables.
+#ifndef SS_STENCIL_TILE_H
+#define SS_STENCIL_TILE_H 16
+#endif
+#ifndef SS_STENCIL_TILE_W
+#define SS_STENCIL_TILE_W 64
+#endif
+#ifndef SS_STENCIL_FRAMES
+#define SS_STENCIL_FRAMES 16
+#endif
+constexpr int kTileH = SS_STENCIL_TILE_H;
+constexpr int kTileW = SS_STENCIL_TILE_W;
+constexpr int kStencilBlock = 256;
+constexpr int kFramesPerBlock = SS_STENCIL_FRAMES;
+// staged pixels per thread for a halo of h pixels
+constexpr int stage_slots(int h) { return ((kTileH + 2 * h) * (kTileW + 2 * h) + kStencilBlock - 1) / kStencilBlock; }
+
+struct StateArgs {
+    const float *frames;
+    const uint32_t *rcoord;
+    const uint8_t *mask;
+    int32_t n_frames;
+    int32_t height, width;
+    int64_t n_pix;
+    int32_t n_bins;
+    int32_t half, min_count;
+    double noise2, n_pick, snr;
+    float noise2f, n_pick_f, snr_f;
+    Workspace ws;
+};
+
+// One work-group owns a kTileH x kTileW tile of pixels for kFramesPerBlock
+// frames.  The tile and its halo of `half` pixels are staged in LDS: radial
+// codes once, then per frame the values and the pixel bits (valid, kept,
+// candidate), computed once per staged pixel.  Candidates of the tile then
+// take the patch test of Sec. 4 from LDS (maximum of v over the valid
+// pixels of the patch, ties to the lower index; at least min_count
+// candidates) and the bits, with kPeak, go to the workspace.
+// Patch test of Sec. 4 from LDS for candidate e: v must be the maximum over
+// the valid pixels of the patch (ties to the lower row-major index, i.e. a
+// neighbour above, or on the same row to the left, wins a tie) with at least
+// min_count candidates in the patch.  For a compile-time half width KH >= 0
+// every neighbour is read before any is tested; KH < 0 walks a runtime half
+// width h.
+template <int KH>
+__device__ inline bool patch_is_peak(const float *v_s, const uint8_t *b_s, int e, int RW, int h, int min_count) {
+    const float vi = v_s[e];
+    if (KH >= 0) {
+        constexpr int P = 2 * (KH < 0 ? 0 : KH) + 1;
+        uint8_t nb[P * P];
+        float nv[P * P];
+#pragma unroll
+        for (int dy = 0; dy < P; ++dy)
+#pragma unroll
+            for (int dx = 0; dx < P; ++dx) {
+                const int q = e + (dy - KH) * RW + (dx - KH);
+                nb[dy * P + dx] = b_s[q];
+                nv[dy * P + dx] = v_s[q];
+            }
+        bool best = true;
+        int count = 0;
+#pragma unroll
+        for (int dy = 0; dy < P; ++dy)
+#pragma unroll
+            for (int dx = 0; dx < P; ++dx) {
+                const uint8_t bq = nb[dy * P + dx];
+                const float vq = nv[dy * P + dx];
+                const bool centre = dy == KH && dx == KH;
+                const bool before = dy < KH || (dy == KH && dx < KH);
+                const bool valid = bq & kValid;
+                best &= !(valid && !centre && (vq > vi || (vq == vi && before)));
+                count += (valid && (bq & kCand)) ? 1 : 0;
+            }
+        return best && count >= min_count;
+    }
+    bool best = true;
+    int count = 0;
+    for (int dy = -h; dy <= h && best; ++dy) {
+        for (int dx = -h; dx <= h; ++dx) {
+            const int q = e + dy * RW + dx;
+            const uint8_t bq = b_s[q];
+            if (!(bq & kValid)) continue;
+            const float vq = v_s[q];
+            const bool before = dy < 0 || (dy == 0 && dx < 0);
+            if ((dy || dx) && (vq > vi || (vq == vi && before))) {
+                best = false;
+                break;
+            }
+            count += (bq & kCand) ? 1 : 0;
+        }
+    }
+    return best && count >= min_count;
+}
+
+template <int kStageSlots, int kH>
+__global__ __launch_bounds__(kStencilBlock) void k_pixel_state(StateArgs a) {
+    extern __shared__ unsigned char lds[];
+    const int h = a.half;
+    const int RW = kTileW + 2 * h, RH = kTileH + 2 * h, RN = RW * RH;
+    uint32_t *rc_s = reinterpret_cast<uint32_t *>(lds);
+    float *v_s = reinterpret_cast<float *>(lds + size_t(RN) * 4);
+    uint8_t *b_s = lds + size_t(RN) * 8;
+
+    const int tx0 = blockIdx.x * kTileW, ty0 = blockIdx.y * kTileH;
+    const int f0 = blockIdx.z * kFramesPerBlock;
+    const int f1 = min(a.n_frames, f0 + kFramesPerBlock);
+    const int tid = threadIdx.x;
+    // e / RW as (e * magic) >> 20, exact for e < 2^20 / RW (RN is far smaller)
+    const uint32_t magic = ((1u << 20) + uint32_t(RW) - 1u) / uint32_t(RW);
+
+    for (int e = tid; e < RN; e += kStencilBlock) {
+        const int r = int((uint32_t(e) * magic) >> 20);
+        const int y = ty0 - h + r, x = tx0 - h + (e - r * RW);
+        uint32_t rc = SS_RC_MASKED;
+        if (y >= 0 && y < a.height && x >= 0 && x < a.width) {
+            const int64_t i = int64_t(y) * a.width + x;
+            rc = a.rcoord[i];
+            if (a.mask && a.mask[i]) rc = SS_RC_MASKED;
+        }
+        rc_s[e] = rc;
+    }
+    __syncthreads();
+
+    for (int f = f0; f < f1; ++f) {
+        const float *__restrict__ fr = a.frames + int64_t(f) * a.n_pix;
+        const Seg *__restrict__ tab = a.ws.table + int64_t(f) * (a.n_bins + 1);
+        const SegF *__restrict__ tabf = a.ws.tablef + int64_t(f) * (a.n_bins + 1);
+        // Staging in three sweeps so that a thread's loads overlap: every
+        // frame value (clamped addresses, masked after), then every table
+        // segment, then the arithmetic.
+        float xv[kStageSlots];
+        uint32_t rcv[kStageSlots];
+#pragma unroll
+        for (int k = 0; k < kStageSlots; ++k) {
+            const int e = tid + k * kStencilBlock;
+            const int ec = min(e, RN - 1);
+            const int r = int((uint32_t(ec) * magic) >> 20);
+            const int y = min(max(ty0 - h + r, 0), a.height - 1);
+            const int x = min(max(tx0 - h + (ec - r * RW), 0), a.width - 1);
+            rcv[k] = e < RN ? rc_s[ec] : SS_RC_MASKED;
+            xv[k] = fr[int64_t(y) * a.width + x];
+        }
+        SegF sg[kStageSlots];
+#pragma unroll
+        for (int k = 0; k < kStageSlots; ++k) sg[k] = tabf[min(int(rcv[k] >> SS_RC_FRAC_BITS), a.n_bins)];
+#pragma unroll
+        for (int k = 0; k < kStageSlots; ++k) {
+            const int e = tid + k * kStencilBlock;
+            if (e < RN) {
+                const uint32_t rc = rcv[k];
+                uint8_t b = 0;
+                if (rc != SS_RC_MASKED)
+                    b = pixel_bits_fast(xv[k], rc, sg[k], tab, a.n_bins, a.noise2f, a.noise2, a.n_pick_f, a.snr_f,
+                                        a.n_pick, a.snr);
+                v_s[e] = rc != SS_RC_MASKED ? xv[k] : 0.0f;
+                b_s[e] = b;
+            }
+        }
+        __syncthreads();
+        uint8_t *__restrict__ bits = a.ws.bits + int64_t(f) * a.n_pix;
+        for (int c = tid; c < kTileH * kTileW; c += kStencilBlock) {
+            const int ly = c / kTileW, lx = c % kTileW;
+            const int y = ty0 + ly, x = tx0 + lx;
+            if (y >= a.height || x >= a.width) continue;
+            const int e = (ly + h) * RW + (lx + h);
+            uint8_t b = b_s[e];
+            if ((b & kCand) && patch_is_peak<kH>(v_s, b_s, e, RW, h, a.min_count)) b |= kPeak;
+            bits[int64_t(y) * a.width + x] = b;
+        }
+        __syncthreads();
+    }
+}
+
+// ---- peak test and record ------------------------------------------------------------
 
 struct PeakSums {
     int count;
     double I, s2, sy, sx;
 };
 
-// Patch test of Sec. 4 for candidate pixel i.  Returns whether i is a peak;
-// with `full` the record sums are complete, otherwise the walk may stop as
-// soon as i is beaten.
-__device__ bool patch_eval(const ClassArgs &a, const float *__restrict__ fr, const Seg *__restrict__ tab,
-                           int64_t i, double vi, bool full, PeakSums &ps) {
+// Record of peak i over the candidates of its patch (background recomputed
+// from the table: peaks are rare).
+__device__ PeakSums peak_record(const ClassArgs &a, const float *__restrict__ fr, const uint8_t *__restrict__ bits,
+                                const Seg *__restrict__ tab, int64_t i) {
     const int y = int(i / a.width);
     const int x = int(i - int64_t(y) * a.width);
     const int y0 = max(0, y - a.half), y1 = min(a.height - 1, y + a.half);
     const int x0 = max(0, x - a.half), x1 = min(a.width - 1, x + a.half);
-    bool is_max = true;
-    ps = PeakSums{0, 0.0, 0.0, 0.0, 0.0};
+    PeakSums ps{0, 0.0, 0.0, 0.0, 0.0};
     for (int yy = y0; yy <= y1; ++yy) {
         for (int xx = x0; xx <= x1; ++xx) {
             const int64_t j = int64_t(yy) * a.width + xx;
-            const float xj = fr[j];
-            const uint32_t rcj = a.rcoord[j];
-            if (!pixel_valid(xj, rcj, a.mask, j)) continue;
-            const double vj = double(xj);
-            if (j != i && (vj > vi || (vj == vi && j < i))) {
-                is_max = false;
-                if (!full) return false;
-            }
+            if (!(bits[j] & kCand)) continue;
             double mu, se;
-            background(rcj, tab, a.n_bins, a.noise2, mu, se);
-            const double d = vj - mu;
-            if (d >= a.snr * se) {
-                ps.count += 1;
-                ps.I += d;
-                ps.s2 += se * se;
-                ps.sy += d * (double(yy) + 0.5);
-                ps.sx += d * (double(xx) + 0.5);
-            }
+            background(a.rcoord[j], tab, a.n_bins, a.noise2, mu, se);
+            const double d = double(fr[j]) - mu;
+            ps.count += 1;
+            ps.I += d;
+            ps.s2 += se * se;
+            ps.sy += d * (double(yy) + 0.5);
+            ps.sx += d * (double(xx) + 0.5);
         }
     }
-    return is_max && ps.count >= a.min_count;
+    return ps;
 }
 
-__device__ inline uint64_t load_flag(const uint64_t *p) {
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ inline void store_flag(uint64_t *p, uint64_t v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Publish this tile's packed counts and return the exclusive prefix.
-__device__ uint64_t look_back(uint64_t *fl, int tile, uint64_t agg) {
-    if (tile == 0) {
-        store_flag(fl, kPrefix | agg);
-        return 0;
+// Inclusive prefix sum over the 64 lanes of a wavefront.
+__device__ inline uint32_t wave_inclusive_scan(uint32_t x) {
+    const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const uint32_t t = __shfl_up(x, off, kWave);
+        if (lane >= off) x += t;
     }
-    store_flag(fl + tile, kAggregate | agg);
-    uint64_t excl = 0;
-    for (int p = tile - 1;; --p) {
-        uint64_t w = load_flag(fl + p);
-        while ((w >> 62) == 0) {
-            __builtin_amdgcn_s_sleep(1);
-            w = load_flag(fl + p);
-        }
-        excl += w & kCountMask;
-        if ((w >> 62) == 2) break;
-    }
-    store_flag(fl + tile, kPrefix | (excl + agg));
-    return excl;
+    return x;
 }
 
+// Kept / peak bits of the kPPT consecutive pixels of thread tid in a tile:
+// 8-byte loads when every frame's bits start 8-byte aligned (n_pix % 8 ==
+// 0), byte loads otherwise.
 template <bool KEEP, bool PEAKS>
-__global__ __launch_bounds__(kBlock) void k_classify(ClassArgs a) {
-    __shared__ uint32_t tile_s;
-    __shared__ int cnt_k[kPPT * kNW];
-    __shared__ int cnt_p[kPPT * kNW];
-    __shared__ uint64_t excl_s;
+__device__ inline void tile_masks(const uint8_t *__restrict__ bits, int64_t n_pix, int64_t p0, uint32_t &kmask,
+                                  uint32_t &pmask) {
+    kmask = 0;
+    pmask = 0;
+    if (p0 + kPPT <= n_pix && (n_pix % 8) == 0) {
+#pragma unroll
+        for (int q = 0; q < kPPT / 8; ++q) {
+            const uint2 w = *reinterpret_cast<const uint2 *>(bits + p0 + 8 * q);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const uint8_t b = uint8_t((k < 4 ? w.x : w.y) >> (8 * (k % 4)));
+                if (KEEP && (b & kKeep)) kmask |= 1u << (8 * q + k);
+                if (PEAKS && (b & kPeak)) pmask |= 1u << (8 * q + k);
+            }
+        }
+    } else {
+        for (int k = 0; k < kPPT; ++k) {
+            const uint8_t b = p0 + k < n_pix ? bits[p0 + k] : 0;
+            if (KEEP && (b & kKeep)) kmask |= 1u << k;
+            if (PEAKS && (b & kPeak)) pmask |= 1u << k;
+        }
+    }
+}
 
-    const int tid = threadIdx.x;
-    const int lane = tid & (kWave - 1);
-    const int wid = tid / kWave;
-    if (tid == 0) tile_s = atomicAdd(a.ws.counter, 1u);
+// Exclusive block-wide scan of one packed u32 per thread; returns this
+// thread's exclusive prefix, and the block total through `total`.
+__device__ inline uint32_t block_exclusive_scan(uint32_t mine, uint32_t *wave_tot, uint32_t &total) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = threadIdx.x / kWave;
+    const uint32_t incl = wave_inclusive_scan(mine);
+    if (lane == kWave - 1) wave_tot[wid] = incl;
     __syncthreads();
-    const uint32_t g = tile_s;
-    const int f = int(g / uint32_t(a.tiles));
-    const int tile = int(g % uint32_t(a.tiles));
-    const int64_t base = int64_t(tile) * kTile;
+    uint32_t before = incl - mine;
+    total = 0;
+#pragma unroll
+    for (int w = 0; w < kNW; ++w) {
+        if (w < wid) before += wave_tot[w];
+        total += wave_tot[w];
+    }
+    return before;
+}
+
+// Per tile: packed count of kept pixels and peaks (each at most kTile).
+template <bool KEEP, bool PEAKS>
+__global__ __launch_bounds__(kBlock) void k_tile_counts(ClassArgs a) {
+    __shared__ uint32_t wave_tot[kNW];
+    const int tile = blockIdx.x, f = blockIdx.y;
+    const int64_t p0 = int64_t(tile) * kTile + int64_t(kPPT) * threadIdx.x;
+    uint32_t kmask, pmask;
+    tile_masks<KEEP, PEAKS>(a.ws.bits + int64_t(f) * a.n_pix, a.n_pix, p0, kmask, pmask);
+    const uint32_t mine = uint32_t(__popc(kmask)) | (uint32_t(__popc(pmask)) << 16);
+    const uint32_t x = uint32_t(wave_sum(int(mine)));
+    if ((threadIdx.x & (kWave - 1)) == 0) wave_tot[threadIdx.x / kWave] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+#pragma unroll
+        for (int w = 0; w < kNW; ++w) t += wave_tot[w];
+        a.ws.counts[int64_t(f) * a.tiles + tile] = t;
+    }
+}
+
+// Per frame: exclusive offsets of every tile, and the frame totals.
+template <bool KEEP, bool PEAKS>
+__global__ __launch_bounds__(kScanBlock) void k_tile_scan(ClassArgs a) {
+    __shared__ uint64_t part[kScanBlock / kWave];
+    __shared__ uint64_t carry_s;
+    const int f = blockIdx.x;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = threadIdx.x / kWave;
+    const uint32_t *cnt = a.ws.counts + int64_t(f) * a.tiles;
+    uint64_t *off = a.ws.offsets + int64_t(f) * a.tiles;
+    if (threadIdx.x == 0) carry_s = 0;
+    __syncthreads();
+    for (int base = 0; base < a.tiles; base += kScanBlock) {
+        const int t = base + int(threadIdx.x);
+        const uint32_t c = t < a.tiles ? cnt[t] : 0u;
+        // widen to kept | peaks << 32 so sums over a frame cannot overflow
+        uint64_t x = uint64_t(c & 0xFFFFu) | (uint64_t(c >> 16) << 32);
+        uint64_t incl = x;
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+            const uint32_t lo = __shfl_up(uint32_t(incl), o, kWave);
+            const uint32_t hi = __shfl_up(uint32_t(incl >> 32), o, kWave);
+            if (lane >= o) incl += (uint64_t(hi) << 32) | lo;
+        }
+        if (lane == kWave - 1) part[wid] = incl;
+        __syncthreads();
+        uint64_t before = carry_s + incl - x, total = 0;
+        for (int w = 0; w < kScanBlock / kWave; ++w) {
+            if (w < wid) before += part[w];
+            total += part[w];
+        }
+        if (t < a.tiles) off[t] = before;
+        __syncthreads();
+        if (threadIdx.x == 0) carry_s += total;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        if (KEEP) a.n_kept[f] = int64_t(carry_s & 0xFFFFFFFFu);
+        if (PEAKS) a.n_peaks[f] = int64_t(carry_s >> 32);
+    }
+}
+
+// Per tile: kept pixels and peak records in pixel order at the tile's
+// offsets; entries beyond the capacities are dropped.
+template <bool KEEP, bool PEAKS>
+__global__ __launch_bounds__(kBlock) void k_tile_write(ClassArgs a) {
+    __shared__ uint32_t wave_tot[kNW];
+    const int tile = blockIdx.x, f = blockIdx.y;
+    const int64_t p0 = int64_t(tile) * kTile + int64_t(kPPT) * threadIdx.x;
     const float *__restrict__ fr = a.frames + int64_t(f) * a.n_pix;
-    const Seg *__restrict__ tab = a.ws.table + int64_t(f) * (a.n_bins + 1);
-
-    float val[kPPT];
-    uint32_t kbits = 0, pbits = 0;
-#pragma unroll
-    for (int k = 0; k < kPPT; ++k) {
-        const int64_t i = base + int64_t(k) * kBlock + tid;
-        bool keep = false, peak = false;
-        val[k] = 0.0f;
-        if (i < a.n_pix) {
-            const float x = fr[i];
-            const uint32_t rc = a.rcoord[i];
-            if (pixel_valid(x, rc, a.mask, i)) {
-                double mu, se;
-                background(rc, tab, a.n_bins, a.noise2, mu, se);
-                const double d = double(x) - mu;
-                val[k] = x;
-                keep = KEEP && d > a.n_pick * se;
-                if (PEAKS && d >= a.snr * se) {
-                    PeakSums ps;
-                    peak = patch_eval(a, fr, tab, i, double(x), false, ps);
-                }
+    const uint8_t *__restrict__ bits = a.ws.bits + int64_t(f) * a.n_pix;
+    uint32_t kmask, pmask;
+    tile_masks<KEEP, PEAKS>(bits, a.n_pix, p0, kmask, pmask);
+    const uint32_t mine = uint32_t(__popc(kmask)) | (uint32_t(__popc(pmask)) << 16);
+    uint32_t total;
+    const uint32_t before = block_exclusive_scan(mine, wave_tot, total);
+    if (total == 0) return;
+    const uint64_t toff = a.ws.offsets[int64_t(f) * a.tiles + tile];
+    int64_t pos_k = int64_t(toff & 0xFFFFFFFFu) + (before & 0xFFFFu);
+    int64_t pos_p = int64_t(toff >> 32) + (before >> 16);
+    if (KEEP) {
+        uint32_t m = kmask;
+        while (m) {
+            const int k = __builtin_ctz(m);
+            m &= m - 1;
+            if (pos_k < a.capacity) {
+                a.kept_index[int64_t(f) * a.capacity + pos_k] = uint32_t(p0 + k);
+                a.kept_value[int64_t(f) * a.capacity + pos_k] = fr[p0 + k];
             }
-        }
-        kbits |= uint32_t(keep) << k;
-        pbits |= uint32_t(peak) << k;
-        const uint64_t km = __ballot(keep);
-        const uint64_t pm = __ballot(peak);
-        if (lane == 0) {
-            cnt_k[k * kNW + wid] = __popcll(km);
-            cnt_p[k * kNW + wid] = __popcll(pm);
+            ++pos_k;
         }
     }
-    __syncthreads();
-
-    // exclusive scan of the (pass, wave) counts in pixel order: one wave,
-    // one slot per lane (kPPT * kNW == 64)
-    static_assert(kPPT * kNW == kWave, "one scan slot per lane");
-    if (wid == 0) {
-        const int ck = cnt_k[lane], cp = cnt_p[lane];
-        int sk = ck, sp = cp;
-#pragma unroll
-        for (int off = 1; off < kWave; off <<= 1) {
-            const int tk = __shfl_up(sk, off, kWave);
-            const int tp = __shfl_up(sp, off, kWave);
-            if (lane >= off) {
-                sk += tk;
-                sp += tp;
-            }
-        }
-        cnt_k[lane] = sk - ck;
-        cnt_p[lane] = sp - cp;
-        const int tot_k = __shfl(sk, kWave - 1, kWave);
-        const int tot_p = __shfl(sp, kWave - 1, kWave);
-        if (lane == 0) {
-            const uint64_t agg = uint64_t(tot_k) | (uint64_t(tot_p) << kPeakShift);
-            const uint64_t excl = look_back(a.ws.flags + int64_t(f) * a.tiles, tile, agg);
-            excl_s = excl;
-            if (tile == a.tiles - 1) {
-                const uint64_t total = excl + agg;
-                if (KEEP) a.n_kept[f] = int64_t(total & ((uint64_t(1) << kPeakShift) - 1));
-                if (PEAKS) a.n_peaks[f] = int64_t((total & kCountMask) >> kPeakShift);
-            }
-        }
-    }
-    __syncthreads();
-    const uint64_t excl = excl_s;
-    const int64_t excl_k = int64_t(excl & ((uint64_t(1) << kPeakShift) - 1));
-    const int64_t excl_p = int64_t((excl & kCountMask) >> kPeakShift);
-
-#pragma unroll
-    for (int k = 0; k < kPPT; ++k) {
-        const bool keep = (kbits >> k) & 1u;
-        const bool peak = (pbits >> k) & 1u;
-        const uint64_t km = __ballot(keep);
-        const uint64_t pm = __ballot(peak);
-        const int64_t i = base + int64_t(k) * kBlock + tid;
-        if (KEEP && keep) {
-            const int64_t pos = excl_k + cnt_k[k * kNW + wid] + lanes_below(km);
-            if (pos < a.capacity) {
-                a.kept_index[int64_t(f) * a.capacity + pos] = uint32_t(i);
-                a.kept_value[int64_t(f) * a.capacity + pos] = val[k];
-            }
-        }
-        if (PEAKS && peak) {
-            const int64_t pos = excl_p + cnt_p[k * kNW + wid] + lanes_below(pm);
-            if (pos < a.peak_capacity) {
-                PeakSums ps;
-                patch_eval(a, fr, tab, i, double(val[k]), true, ps);
+    if (PEAKS && pmask) {
+        const Seg *__restrict__ tab = a.ws.table + int64_t(f) * (a.n_bins + 1);
+        uint32_t m = pmask;
+        while (m) {
+            const int k = __builtin_ctz(m);
+            m &= m - 1;
+            if (pos_p < a.peak_capacity) {
+                const int64_t i = p0 + k;
+                const PeakSums ps = peak_record(a, fr, bits, tab, i);
                 ss_peak rec;
                 rec.index = uint32_t(i);
                 rec.y = float(ps.sy / ps.I);
                 rec.x = float(ps.sx / ps.I);
                 rec.intensity = float(ps.I);
                 rec.sigma = float(sqrt(ps.s2));
-                a.peaks[int64_t(f) * a.peak_capacity + pos] = rec;
+                a.peaks[int64_t(f) * a.peak_capacity + pos_p] = rec;
             }
+            ++pos_p;
         }
     }
+}
+
+template <bool KEEP, bool PEAKS>
+void launch_compaction(const ClassArgs &a, hipStream_t stream) {
+    const dim3 grid(uint32_t(a.tiles), uint32_t(a.n_frames));
+    k_tile_counts<KEEP, PEAKS><<<grid, kBlock, 0, stream>>>(a);
+    k_tile_scan<KEEP, PEAKS><<<dim3(uint32_t(a.n_frames)), kScanBlock, 0, stream>>>(a);
+    k_tile_write<KEEP, PEAKS><<<grid, kBlock, 0, stream>>>(a);
 }
 
 }  // namespace
@@ -390,8 +634,7 @@ extern "C" int ss_classify(const float *frames, const uint8_t *mask, int32_t n_f
     if (!radial || !profile || !p) return SS_EINVAL;
     if (n_frames < 0 || height < 0 || width < 0 || capacity < 0 || peak_capacity < 0) return SS_ESIZE;
     const int64_t n_pix = int64_t(height) * width;
-    if (n_pix >= (int64_t(1) << 31) || int64_t(n_frames) * int64_t(tiles_of(n_pix)) >= (int64_t(1) << 32))
-        return SS_ESIZE;
+    if (n_pix >= (int64_t(1) << 31) || n_frames > 65535) return SS_ESIZE;
     if (radial->n_bins <= 0 || radial->n_bins > SS_MAX_BINS) return SS_ESIZE;
     if (p->patch < 1 || p->patch > SS_MAX_PATCH || (p->patch % 2) == 0) return SS_EINVAL;
     const bool keep = kept_index || kept_value || n_kept;
@@ -404,15 +647,47 @@ extern "C" int ss_classify(const float *frames, const uint8_t *mask, int32_t n_f
     if (ws_bytes < workspace_bytes(n_frames, n_pix, radial->n_bins)) return SS_ESIZE;
 
     const int32_t tiles = int32_t(tiles_of(n_pix));
-    Workspace ws = carve(workspace, n_frames, n_pix);
+    Workspace ws = carve(workspace, n_frames, n_pix, radial->n_bins);
     k_profile_table<<<dim3(uint32_t(n_frames)), kTableBlock, 0, stream>>>(
         profile->mean, profile->std, profile->n_members, radial->n_bins, ws, tiles, keep ? n_kept : nullptr,
         pk ? n_peaks : nullptr);
     SS_RETURN_IF_LAUNCH_FAILED();
     if (tiles == 0) return SS_OK;
+    {
+        StateArgs sa;
+        sa.frames = frames;
+        sa.rcoord = radial->rcoord;
+        sa.mask = mask;
+        sa.n_frames = n_frames;
+        sa.height = height;
+        sa.width = width;
+        sa.n_pix = n_pix;
+        sa.n_bins = radial->n_bins;
+        sa.half = p->patch / 2;
+        sa.min_count = p->min_count;
+        sa.noise2 = double(p->noise) * double(p->noise);
+        sa.n_pick = double(p->n_pick);
+        sa.snr = double(p->snr);
+        sa.noise2f = float(sa.noise2);
+        sa.n_pick_f = p->n_pick;
+        sa.snr_f = p->snr;
+        sa.ws = ws;
+        const int h = sa.half;
+        const size_t lds = size_t(kTileW + 2 * h) * size_t(kTileH + 2 * h) * 9;
+        const dim3 grid(uint32_t((width + kTileW - 1) / kTileW), uint32_t((height + kTileH - 1) / kTileH),
+                        uint32_t((n_frames + kFramesPerBlock - 1) / kFramesPerBlock));
+        // staging registers sized to the halo; patches 1, 3 and 5 unrolled
+        if (h == 0) k_pixel_state<stage_slots(0), 0><<<grid, kStencilBlock, lds, stream>>>(sa);
+        else if (h == 1) k_pixel_state<stage_slots(1), 1><<<grid, kStencilBlock, lds, stream>>>(sa);
+        else if (h == 2) k_pixel_state<stage_slots(2), 2><<<grid, kStencilBlock, lds, stream>>>(sa);
+        else if (h <= 4) k_pixel_state<stage_slots(4), -1><<<grid, kStencilBlock, lds, stream>>>(sa);
+        else k_pixel_state<stage_slots(SS_MAX_PATCH / 2), -1><<<grid, kStencilBlock, lds, stream>>>(sa);
+        SS_RETURN_IF_LAUNCH_FAILED();
+    }
 
     ClassArgs a;
     a.frames = frames;
+    a.n_frames = n_frames;
     a.mask = mask;
     a.rcoord = radial->rcoord;
     a.n_pix = n_pix;
@@ -433,10 +708,9 @@ extern "C" int ss_classify(const float *frames, const uint8_t *mask, int32_t n_f
     a.peak_capacity = peak_capacity;
     a.n_peaks = n_peaks;
     a.ws = ws;
-    const dim3 grid(uint32_t(int64_t(tiles) * n_frames));
-    if (keep && pk) k_classify<true, true><<<grid, kBlock, 0, stream>>>(a);
-    else if (keep) k_classify<true, false><<<grid, kBlock, 0, stream>>>(a);
-    else k_classify<false, true><<<grid, kBlock, 0, stream>>>(a);
+    if (keep && pk) launch_compaction<true, true>(a, stream);
+    else if (keep) launch_compaction<true, false>(a, stream);
+    else launch_compaction<false, true>(a, stream);
     SS_RETURN_IF_LAUNCH_FAILED();
     return SS_OK;
 }

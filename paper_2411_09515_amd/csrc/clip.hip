@@ -41,6 +41,9 @@ struct ClipArgs {
     const int32_t *indices;
     const float *weight;
     int64_t nnz;
+    const int32_t *bin_order;  // bins of this launch: bin_order[order_base + i], or i when null
+    int32_t order_base;
+    int32_t launch_bins;       // bins covered by this launch
     double cutoff;
     int32_t max_iter;
     int32_t model;
@@ -89,10 +92,21 @@ __device__ inline bool member_ok(float x, float w, const uint8_t *mask, int32_t 
     return isfinite(x) && w > 0.0f && !(mask && mask[idx]);
 }
 
-// The clip decision of eq. clip (strict, two-sided).
-__device__ inline bool clipped(float x, double mean, double thr) {
-    return fabs(double(x) - mean) > thr;
+// The clip decision of eq. clip (strict, two-sided), |v - mean| > thr, taken
+// as v > hi or v < lo with hi = mean + thr and lo = mean - thr in float64.
+// For a float32 v, v > hi exactly when v > RD32(hi) (no float32 lies
+// strictly between RD32(hi) and hi), and v < lo exactly when v < RU32(lo),
+// so the per-member test is two float32 compares against bounds rounded
+// once per pass.
+struct ClipBounds {
+    float lo, hi;
+};
+
+__device__ inline ClipBounds clip_bounds(double mean, double thr) {
+    return ClipBounds{__double2float_ru(mean - thr), __double2float_rd(mean + thr)};
 }
+
+__device__ inline bool clipped(float x, ClipBounds b) { return x > b.hi || x < b.lo; }
 
 // Cut-off of pass k: the fixed value, or Chauvenet's value for the current
 // size (eq. chauvenet); <= 0 means nothing can be removed.
@@ -124,6 +138,28 @@ __device__ inline void add_member(double (&s)[NSUM], double w, double d, double 
     s[S_PV] += w2 * pv;
     s[S_N] += 1.0;
 }
+
+// Work-group -> (frame, bin).  Work-groups are dispatched to the 8 XCDs
+// round robin (work-group g runs on XCD g % 8), so work-group g is given the
+// item x * per + g / 8 of the frame-major list (frame, bin), x = g % 8: each
+// XCD walks a contiguous run of that list, and neighbouring bins of a frame,
+// whose rings share cache lines, run back to back on the same L2.  Returns
+// false for the padding work-groups beyond the list.
+__device__ inline bool block_item(const ClipArgs &a, int &f, int &bin) {
+    const uint32_t nb = uint32_t(a.launch_bins);
+    const uint32_t total = uint32_t(a.n_frames) * nb;
+    const uint32_t per = (total + 7u) / 8u;
+    const uint32_t g = blockIdx.x;
+    const uint32_t item = (g % 8u) * per + g / 8u;
+    if (g / 8u >= per || item >= total) return false;
+    f = int(item / nb);
+    const int local = int(item % nb);
+    bin = a.bin_order ? a.bin_order[a.order_base + local] : local;
+    return uint32_t(bin) < uint32_t(a.n_bins);
+}
+
+// Grid size for block_item: 8 runs of ceil(total / 8) work-groups.
+inline uint32_t item_grid(int64_t total) { return uint32_t(8 * ((total + 7) / 8)); }
 
 __device__ inline void row_bounds(const ClipArgs &a, int bin, int64_t &start, int64_t &end) {
     // clamped to [0, nnz] so a malformed indptr cannot read past the arrays
@@ -158,6 +194,7 @@ __device__ inline double first_shift(const ClipArgs &a, const float *fr, int64_t
 // Pass control, computed by one thread and published to the work-group.
 struct PassCtl {
     double mean, thr, K;
+    ClipBounds bounds;
     int go, n_iter, converged, refresh;
 };
 
@@ -193,6 +230,7 @@ __device__ inline void plan(const ClipArgs &a, const double (&s)[NSUM], PassCtl 
         return;
     }
     c.thr = ncut * ((a.model == SS_POISSON) ? st.pstd : st.std);
+    c.bounds = clip_bounds(c.mean, c.thr);
     c.go = 1;
 }
 
@@ -205,13 +243,14 @@ template <int BLOCK, int EPT>
 __global__ __launch_bounds__(BLOCK) void k_clip_regs(ClipArgs a) {
     static_assert(EPT <= 64, "member flags live in one 64-bit word");
     constexpr int NW = BLOCK / kWave;
+    __shared__ float w_s[EPT * BLOCK];
     __shared__ double part[NSUM * NW];
     __shared__ double tot[NSUM];
     __shared__ double state[NSUM];
     __shared__ PassCtl ctl;
 
-    const int bin = int(blockIdx.x / uint32_t(a.n_frames));
-    const int f = int(blockIdx.x % uint32_t(a.n_frames));
+    int f, bin;
+    if (!block_item(a, f, bin)) return;
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const int wid = tid / kWave;
@@ -236,9 +275,11 @@ __global__ __launch_bounds__(BLOCK) void k_clip_regs(ClipArgs a) {
     double K = first_shift(a, fr, start, end);
 
     // Buffer views of the row and of the frame: every load below is issued
-    // unconditionally (slots past the row end read 0 and are masked after),
-    // so all EPT gathers of a thread can be in flight together, with one
-    // 32-bit offset register per slot and the slot's stride in a scalar.
+    // unconditionally (slots past the row end read 0 and are masked after)
+    // with one 32-bit offset register per slot and the slot's stride in a
+    // scalar.  The row's indices and weights are all requested before any
+    // gather, so a work-group waits for two memory round trips in total;
+    // the weights then live in LDS for the rest of the kernel.
     const __amdgpu_buffer_rsrc_t ri = buffer_rsrc(idxs, uint32_t(len) * 4u);
     const __amdgpu_buffer_rsrc_t rw = buffer_rsrc(wts, uint32_t(len) * 4u);
     const __amdgpu_buffer_rsrc_t rf = buffer_rsrc(fr, uint32_t(a.n_pix) * 4u);
@@ -255,11 +296,12 @@ __global__ __launch_bounds__(BLOCK) void k_clip_regs(ClipArgs a) {
         }
 #pragma unroll
         for (int e = 0; e < EPT; ++e) v[e] = buffer_load_f32(rf, uint32_t(ix[e]) * 4u, 0u);
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) w_s[e * BLOCK + tid] = wt[e];
         double t[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
-            const bool ok = (e * BLOCK + tid < len) && uint32_t(ix[e]) <= last && isfinite(v[e]) &&
-                            wt[e] > 0.0f;
+            const bool ok = (e * BLOCK + tid < len) && uint32_t(ix[e]) <= last && isfinite(v[e]) && wt[e] > 0.0f;
             act |= uint64_t(ok) << e;
             const double wd = ok ? double(wt[e]) : 0.0;
             const double d = ok ? double(v[e]) - K : 0.0;
@@ -277,15 +319,13 @@ __global__ __launch_bounds__(BLOCK) void k_clip_regs(ClipArgs a) {
             state[S_PV] = 0.0;
         }
     }
-    // sweep 2: deviations around the first mean (two-pass VV); the weights
-    // are re-read (cache hits) rather than kept in registers
+    // sweep 2: deviations around the first mean (two-pass VV)
     {
         double t[3] = {0.0, 0.0, 0.0};
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
             const bool ok = (act >> e) & 1u;
-            const float w = buffer_load_f32(rw, tofs, uint32_t(e * BLOCK) * 4u);
-            const double wd = ok ? double(w) : 0.0;
+            const double wd = ok ? double(w_s[e * BLOCK + tid]) : 0.0;
             const double d = ok ? double(v[e]) - K : 0.0;
             const double w2 = wd * wd;
             t[0] += wd * d;
@@ -297,7 +337,7 @@ __global__ __launch_bounds__(BLOCK) void k_clip_regs(ClipArgs a) {
             state[S_WD] = t[0];
             state[S_W2D] = t[1];
             state[S_W2D2] = t[2];
-            PassCtl c{0.0, 0.0, K, 0, 0, 0, 0};
+            PassCtl c{0.0, 0.0, K, ClipBounds{0.0f, 0.0f}, 0, 0, 0, 0};
             double sv[NSUM];
             load_state(state, sv);
             plan(a, sv, c, 0, false);
@@ -313,11 +353,8 @@ __global__ __launch_bounds__(BLOCK) void k_clip_regs(ClipArgs a) {
             const double Kn = ctl.mean;
             double t[NSUM] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int e = 0; e < EPT; ++e) {
-                const bool ok = (act >> e) & 1u;
-                const float w = buffer_load_f32(rw, tofs, uint32_t(e * BLOCK) * 4u);
-                if (ok) add_member(t, double(w), double(v[e]) - Kn, 0.0);
-            }
+            for (int e = 0; e < EPT; ++e)
+                if ((act >> e) & 1u) add_member(t, double(w_s[e * BLOCK + tid]), double(v[e]) - Kn, 0.0);
             block_sum<NSUM, BLOCK>(t, part, tot);
             if (tid == 0) {
                 t[S_N] = rint(t[S_N]);
@@ -331,47 +368,52 @@ __global__ __launch_bounds__(BLOCK) void k_clip_regs(ClipArgs a) {
             __syncthreads();
             if (!ctl.go) break;
         }
-        const double m = ctl.mean, thr = ctl.thr, Kc = ctl.K;
+        const ClipBounds bnd = ctl.bounds;
+        const double Kc = ctl.K;
         uint64_t rem = 0;
 #pragma unroll
         for (int e = 0; e < EPT; ++e)
-            if (((act >> e) & 1u) && clipped(v[e], m, thr)) rem |= uint64_t(1) << e;
+            if (((act >> e) & 1u) && clipped(v[e], bnd)) rem |= uint64_t(1) << e;
         act &= ~rem;
+        // per-wave sums of the removed members; slots where no lane of the
+        // wave removed anything are skipped (wave-uniform test)
+        double r[NSUM] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         if (__ballot(rem != 0) != 0) {
-            double r[NSUM] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int e = 0; e < EPT; ++e)
-                if ((rem >> e) & 1u)
-                    add_member(r, double(buffer_load_f32(rw, tofs, uint32_t(e * BLOCK) * 4u)), double(v[e]) - Kc,
-                               0.0);
+            for (int e = 0; e < EPT; ++e) {
+                const bool out = (rem >> e) & 1u;
+                if (__ballot(out) == 0) continue;
+                if (out) add_member(r, double(w_s[e * BLOCK + tid]), double(v[e]) - Kc, 0.0);
+            }
 #pragma unroll
             for (int q = 0; q < NSUM; ++q) r[q] = wave_sum(r[q]);
-            if (lane == 0) {
+        }
+        if (lane == 0) {
 #pragma unroll
-                for (int q = 0; q < NSUM; ++q) part[q * NW + wid] = r[q];
-            }
-        } else if (lane == 0) {
-#pragma unroll
-            for (int q = 0; q < NSUM; ++q) part[q * NW + wid] = 0.0;
+            for (int q = 0; q < NSUM; ++q) part[q * NW + wid] = r[q];
         }
         __syncthreads();
-        if (tid == 0) {
-            double n_rem = 0.0;
-            for (int q = 0; q < NSUM; ++q) {
-                double x = 0.0;
-                for (int w = 0; w < NW; ++w) x += part[q * NW + w];
-                if (q == S_N) n_rem = x;
-                state[q] -= x;
-            }
-            state[S_N] = rint(state[S_N]);
-            PassCtl c = ctl;
-            after_pass(c, n_rem >= 0.5);
-            if (c.go) {
+        // wave 0 adds the per-wave sums (lane w reads wave w's), updates
+        // the running sums and plans the next pass
+        if (wid == 0) {
+            double x[NSUM];
+#pragma unroll
+            for (int q = 0; q < NSUM; ++q) x[q] = lane < NW ? part[q * NW + lane] : 0.0;
+#pragma unroll
+            for (int q = 0; q < NSUM; ++q) x[q] = wave_sum(x[q]);
+            if (lane == 0) {
                 double sv[NSUM];
                 load_state(state, sv);
-                plan(a, sv, c, k + 1, true);
+#pragma unroll
+                for (int q = 0; q < NSUM; ++q) sv[q] -= x[q];
+                sv[S_N] = rint(sv[S_N]);
+#pragma unroll
+                for (int q = 0; q < NSUM; ++q) state[q] = sv[q];
+                PassCtl c = ctl;
+                after_pass(c, x[S_N] >= 0.5);
+                if (c.go) plan(a, sv, c, k + 1, true);
+                ctl = c;
             }
-            ctl = c;
         }
         __syncthreads();
     }
@@ -389,11 +431,10 @@ __global__ __launch_bounds__(BLOCK) void k_clip_stream(ClipArgs a) {
     constexpr int NW = BLOCK / kWave;
     __shared__ double part[NSUM * NW];
     __shared__ double tot[NSUM];
-    __shared__ double hist_mean[SS_MAX_ITER];
-    __shared__ double hist_thr[SS_MAX_ITER];
+    __shared__ ClipBounds hist[SS_MAX_ITER];
 
-    const int bin = int(blockIdx.x / uint32_t(a.n_frames));
-    const int f = int(blockIdx.x % uint32_t(a.n_frames));
+    int f, bin;
+    if (!block_item(a, f, bin)) return;
     const int tid = threadIdx.x;
     int64_t start, end;
     row_bounds(a, bin, start, end);
@@ -440,7 +481,7 @@ __global__ __launch_bounds__(BLOCK) void k_clip_stream(ClipArgs a) {
         s[S_PV] = t[3];
     }
     // every thread holds the same block-reduced sums and runs the same plan
-    PassCtl c{0.0, 0.0, K, 0, 0, 0, 0};
+    PassCtl c{0.0, 0.0, K, ClipBounds{0.0f, 0.0f}, 0, 0, 0, 0};
     plan(a, s, c, 0, false);
     for (int k = 0; c.go; ++k) {
         if (c.refresh) {
@@ -453,7 +494,7 @@ __global__ __launch_bounds__(BLOCK) void k_clip_stream(ClipArgs a) {
                 const float x = gather(fr, idx, a.n_pix);
                 if (!member_ok(x, wt, a.mask, idx)) continue;
                 bool alive = true;
-                for (int q = 0; q < k && alive; ++q) alive = !clipped(x, hist_mean[q], hist_thr[q]);
+                for (int q = 0; q < k && alive; ++q) alive = !clipped(x, hist[q]);
                 if (alive) {
                     const double pv = need_pv ? poisson_var(x, a.norm ? a.norm[idx] : 1.0f, a.dark_var) : 0.0;
                     add_member(t, double(wt), double(x) - Kn, pv);
@@ -467,10 +508,7 @@ __global__ __launch_bounds__(BLOCK) void k_clip_stream(ClipArgs a) {
             plan(a, s, c, k, false);
             if (!c.go) break;
         }
-        if (tid == 0) {
-            hist_mean[k] = c.mean;
-            hist_thr[k] = c.thr;
-        }
+        if (tid == 0) hist[k] = c.bounds;
         __syncthreads();
         double r[NSUM] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         for (int64_t j = start + tid; j < end; j += BLOCK) {
@@ -479,8 +517,8 @@ __global__ __launch_bounds__(BLOCK) void k_clip_stream(ClipArgs a) {
             const float x = gather(fr, idx, a.n_pix);
             if (!member_ok(x, wt, a.mask, idx)) continue;
             bool alive = true;
-            for (int q = 0; q < k && alive; ++q) alive = !clipped(x, hist_mean[q], hist_thr[q]);
-            if (alive && clipped(x, c.mean, c.thr)) {
+            for (int q = 0; q < k && alive; ++q) alive = !clipped(x, hist[q]);
+            if (alive && clipped(x, c.bounds)) {
                 const double pv = need_pv ? poisson_var(x, a.norm ? a.norm[idx] : 1.0f, a.dark_var) : 0.0;
                 add_member(r, double(wt), double(x) - c.K, pv);
             }
@@ -502,20 +540,62 @@ void launch_regs(const ClipArgs &a, uint32_t grid, hipStream_t stream) {
     k_clip_regs<BLOCK, EPT><<<dim3(grid), BLOCK, 0, stream>>>(a);
 }
 
-// Register variant with the smallest footprint that holds the longest row;
-// otherwise the streaming variant.
-void dispatch(const ClipArgs &a, int32_t max_row, uint32_t grid, hipStream_t stream) {
+template <int BLOCK>
+void launch_stream(const ClipArgs &a, uint32_t grid, hipStream_t stream) {
+    k_clip_stream<BLOCK><<<dim3(grid), BLOCK, 0, stream>>>(a);
+}
+
+// Work-group shape of row-length class c (rows up to ss_class_rows(c)).
+void launch_class(const ClipArgs &a, int c, uint32_t grid, hipStream_t stream) {
+    switch (c) {
+        case 0: launch_regs<256, 4>(a, grid, stream); break;
+        case 1: launch_regs<256, 8>(a, grid, stream); break;
+        case 2: launch_regs<256, 16>(a, grid, stream); break;
+        case 3: launch_regs<512, 16>(a, grid, stream); break;
+        case 4: launch_regs<1024, 16>(a, grid, stream); break;
+        case 5: launch_regs<1024, 24>(a, grid, stream); break;
+        default: launch_stream<1024>(a, grid, stream); break;
+    }
+}
+
+int class_of(int32_t rows) {
+    int c = 0;
+    while (c < SS_N_CLASSES - 1 && rows > ss_class_rows(c)) ++c;
+    return c;
+}
+
+// One launch per row-length class when the CSR carries a schedule (register
+// kernels sized to the class); otherwise one launch sized to the longest
+// row.  The Poisson and hybrid models and an extra mask take the streaming
+// kernel.
+void dispatch(ClipArgs a, const ss_csr *csr, int n_frames, hipStream_t stream) {
     const bool regs = a.model == SS_AZIMUTHAL && a.mask == nullptr && a.n_pix < (int64_t(1) << 30);
-    if (regs && max_row <= 256 * 4) launch_regs<256, 4>(a, grid, stream);
-    else if (regs && max_row <= 256 * 8) launch_regs<256, 8>(a, grid, stream);
-    else if (regs && max_row <= 256 * 16) launch_regs<256, 16>(a, grid, stream);
-    else if (regs && max_row <= 512 * 16) launch_regs<512, 16>(a, grid, stream);
-    else if (regs && max_row <= 512 * 24) launch_regs<512, 24>(a, grid, stream);
-    else if (regs && max_row <= 512 * 32) launch_regs<512, 32>(a, grid, stream);
-    else if (regs && max_row <= 512 * 40) launch_regs<512, 40>(a, grid, stream);
-    else if (regs && max_row <= 1024 * 24) launch_regs<1024, 24>(a, grid, stream);
-    else if (max_row <= 4096) k_clip_stream<256><<<dim3(grid), 256, 0, stream>>>(a);
-    else k_clip_stream<1024><<<dim3(grid), 1024, 0, stream>>>(a);
+    if (!regs) {
+        a.bin_order = nullptr;
+        a.order_base = 0;
+        a.launch_bins = a.n_bins;
+        const uint32_t grid = item_grid(int64_t(a.n_bins) * n_frames);
+        if (csr->max_row <= 4096) launch_stream<256>(a, grid, stream);
+        else launch_stream<1024>(a, grid, stream);
+        return;
+    }
+    if (csr->bin_order == nullptr) {
+        a.bin_order = nullptr;
+        a.order_base = 0;
+        a.launch_bins = a.n_bins;
+        launch_class(a, class_of(csr->max_row), item_grid(int64_t(a.n_bins) * n_frames), stream);
+        return;
+    }
+    int32_t base = 0;
+    for (int c = SS_N_CLASSES - 1; c >= 0; --c) {
+        const int32_t cnt = csr->class_count[c];
+        if (cnt <= 0) continue;
+        a.bin_order = csr->bin_order;
+        a.order_base = base;
+        a.launch_bins = cnt;
+        launch_class(a, c, item_grid(int64_t(cnt) * n_frames), stream);
+        base += cnt;
+    }
 }
 
 }  // namespace
@@ -538,8 +618,8 @@ static int clip_entry(const float *frames, const float *norm, const uint8_t *mas
     if (!frames || !csr->indptr || (csr->nnz > 0 && (!csr->indices || !csr->weight)) || !out->mean ||
         !out->std || !out->sem || !out->sum_w || !out->n_members || !out->n_iter || !out->converged)
         return SS_EINVAL;
-    const int64_t grid = int64_t(csr->n_bins) * n_frames;
-    if (grid >= (int64_t(1) << 31)) return SS_ESIZE;
+    const int64_t items = int64_t(csr->n_bins) * n_frames;
+    if (items >= (int64_t(1) << 31) - 8) return SS_ESIZE;
     ss::ClipArgs a;
     a.frames = frames;
     a.n_pix = csr->n_pix;
@@ -551,6 +631,9 @@ static int clip_entry(const float *frames, const float *norm, const uint8_t *mas
     a.indices = csr->indices;
     a.weight = csr->weight;
     a.nnz = csr->nnz;
+    a.bin_order = nullptr;
+    a.order_base = 0;
+    a.launch_bins = csr->n_bins;
     a.cutoff = double(p->cutoff);
     a.max_iter = integrate_only ? 0 : p->max_iter;
     a.model = p->error_model;
@@ -562,7 +645,15 @@ static int clip_entry(const float *frames, const float *norm, const uint8_t *mas
     a.n_members = out->n_members;
     a.n_iter = out->n_iter;
     a.converged = out->converged;
-    ss::dispatch(a, csr->max_row, uint32_t(grid), stream);
+    if (csr->bin_order) {
+        int64_t sum = 0;
+        for (int c = 0; c < SS_N_CLASSES; ++c) {
+            if (csr->class_count[c] < 0) return SS_EINVAL;
+            sum += csr->class_count[c];
+        }
+        if (sum != csr->n_bins) return SS_EINVAL;
+    }
+    ss::dispatch(a, csr, n_frames, stream);
     SS_RETURN_IF_LAUNCH_FAILED();
     return SS_OK;
 }

@@ -16,11 +16,29 @@ namespace ss {
 
 constexpr int kWave = 64;
 
-// Butterfly sum over the 64 lanes of a wavefront; every lane gets the total.
-__device__ inline double wave_sum(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
-    return v;
+// Move a double across lanes with a DPP control (both 32-bit halves).
+template <int CTRL>
+__device__ inline double dpp_move(double x) {
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ inline double readlane(double x, int lane) {
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), lane),
+                            __builtin_amdgcn_readlane(__double2loint(x), lane));
+}
+
+// Sum over the 64 lanes of a wavefront; every lane gets the same total.
+// Within each row of 16 lanes: quad_perm [1,0,3,2], quad_perm [2,3,0,1],
+// row_half_mirror and row_mirror leave the row's sum in every lane; the four
+// row sums are then added in a fixed order.
+__device__ inline double wave_sum(double x) {
+    x += dpp_move<0xB1>(x);
+    x += dpp_move<0x4E>(x);
+    x += dpp_move<0x141>(x);
+    x += dpp_move<0x140>(x);
+    return (readlane(x, 0) + readlane(x, 16)) + (readlane(x, 32) + readlane(x, 48));
 }
 
 __device__ inline int wave_sum(int v) {
@@ -45,14 +63,11 @@ __device__ inline void block_sum(double (&v)[N], double *part, double *tot) {
         for (int k = 0; k < N; ++k) part[k * NW + wid] = v[k];
     }
     __syncthreads();
-    if (wid == 0) {
+    if (threadIdx.x < N) {
+        double x = 0.0;
 #pragma unroll
-        for (int k = 0; k < N; ++k) {
-            double x = lane < NW ? part[k * NW + lane] : 0.0;
-#pragma unroll
-            for (int off = NW / 2; off > 0; off >>= 1) x += __shfl_xor(x, off, kWave);
-            if (lane == 0) tot[k] = x;
-        }
+        for (int w = 0; w < NW; ++w) x += part[threadIdx.x * NW + w];
+        tot[threadIdx.x] = x;
     }
     __syncthreads();
 #pragma unroll

@@ -163,6 +163,36 @@ extern "C" int ss_radial_coords(int32_t height, int32_t width, double pixel_m, d
     return SS_OK;
 }
 
+namespace {
+// Longest row of each class but the last (which takes any length); the clip
+// sizes its work-groups to these (work-group threads x values per thread).
+constexpr int32_t kClassRows[SS_N_CLASSES - 1] = {1024, 2048, 4096, 8192, 16384, 24576};
+}  // namespace
+
+extern "C" int32_t ss_class_rows(int32_t c) {
+    return (c >= 0 && c < SS_N_CLASSES - 1) ? kClassRows[c] : 0;
+}
+
+extern "C" int ss_csr_schedule(const int64_t *indptr, int32_t n_bins, int32_t *bin_order, int32_t *class_count) {
+    if (!indptr || !bin_order || !class_count) return SS_EINVAL;
+    if (n_bins <= 0 || n_bins > SS_MAX_BINS) return SS_ESIZE;
+    std::vector<int32_t> cls(static_cast<size_t>(n_bins), 0);
+    for (int32_t c = 0; c < SS_N_CLASSES; ++c) class_count[c] = 0;
+    for (int32_t r = 0; r < n_bins; ++r) {
+        const int64_t len = indptr[r + 1] - indptr[r];
+        if (len < 0) return SS_EINVAL;
+        int32_t c = 0;
+        while (c < SS_N_CLASSES - 1 && len > kClassRows[c]) ++c;
+        cls[size_t(r)] = c;
+        ++class_count[c];
+    }
+    int32_t at = 0;
+    for (int32_t c = SS_N_CLASSES - 1; c >= 0; --c)
+        for (int32_t r = 0; r < n_bins; ++r)
+            if (cls[size_t(r)] == c) bin_order[at++] = r;
+    return SS_OK;
+}
+
 extern "C" const char *ss_strerror(int code) {
     switch (code) {
         case SS_OK: return "ok";

@@ -19,7 +19,7 @@ HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))
 
 def _declared():
     text = open(HEADER).read()
-    return sorted(set(re.findall(r"^(?:int|size_t|const char \*)\s*(ss_\w+)\s*\(", text, re.M)))
+    return sorted(set(re.findall(r"^(?:int|int32_t|size_t|const char \*)\s*(ss_\w+)\s*\(", text, re.M)))
 
 
 def test_library_exports_every_declared_symbol():
@@ -111,7 +111,7 @@ def test_device_calls_reject_bad_arguments_before_launch():
     assert L.ss_correct(fake, -1, 16, fake, fake, None, fake, None, None) == B.SS_ESIZE
     assert L.ss_correct(fake, 1, 1 << 31, fake, fake, None, fake, None, None) == B.SS_ESIZE
     assert L.ss_correct(fake, 0, 16, fake, fake, None, fake, None, None) == B.SS_OK
-    csr = B.Csr(10, 5, 100, 50, 4096, 4096, 4096)
+    csr = B.Csr(10, 5, 100, 50, 4096, 4096, 4096, None)
     prof = B.Profile(*([4096] * 7))
     good = B.Params(3.0, 5, 0, 0.0, 3.0, 0.0, 3.0, 3, 3)
     bad_iter = B.Params(3.0, B.SS_MAX_ITER + 1, 0, 0.0, 3.0, 0.0, 3.0, 3, 3)
@@ -121,7 +121,7 @@ def test_device_calls_reject_bad_arguments_before_launch():
     assert L.ss_sigma_clip(fake, None, None, 1, ref(csr), ref(bad_model), ref(prof), None) == B.SS_EINVAL
     assert L.ss_sigma_clip(None, None, None, 1, ref(csr), ref(good), ref(prof), None) == B.SS_EINVAL
     assert L.ss_sigma_clip(fake, None, None, 0, ref(csr), ref(good), ref(prof), None) == B.SS_OK
-    big = B.Csr(B.SS_MAX_BINS + 1, 5, 100, 50, 4096, 4096, 4096)
+    big = B.Csr(B.SS_MAX_BINS + 1, 5, 100, 50, 4096, 4096, 4096, None)
     assert L.ss_sigma_clip(fake, None, None, 1, ref(big), ref(good), ref(prof), None) == B.SS_ESIZE
     # integrate ignores max_iter
     assert L.ss_integrate(fake, None, None, 0, ref(csr), ref(bad_iter), ref(prof), None) == B.SS_OK
@@ -140,3 +140,31 @@ def test_device_calls_reject_bad_arguments_before_launch():
                          None) == B.SS_ESIZE
     assert L.ss_compress(*args, ref(good), None, fake, 8, fake, fake, need, None) == B.SS_EINVAL
     assert L.ss_peakfind(*args, ref(good), None, 8, fake, fake, need, None) == B.SS_EINVAL
+
+
+def test_schedule_groups_rows_by_class():
+    L = B.lib()
+    rng = np.random.default_rng(4)
+    n_bins = 300
+    lens = rng.integers(0, 30000, n_bins)
+    indptr = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    order = np.zeros(n_bins, dtype=np.int32)
+    counts = np.zeros(B.SS_N_CLASSES, dtype=np.int32)
+    assert L.ss_csr_schedule(indptr.ctypes.data, n_bins, order.ctypes.data, counts.ctypes.data) == B.SS_OK
+    assert sorted(order.tolist()) == list(range(n_bins)) and counts.sum() == n_bins
+    limits = [L.ss_class_rows(c) for c in range(B.SS_N_CLASSES - 1)] + [1 << 40]
+    assert limits[:6] == [1024, 2048, 4096, 8192, 16384, 24576]
+    at = 0
+    for c in range(B.SS_N_CLASSES - 1, -1, -1):
+        chunk = order[at: at + counts[c]]
+        at += counts[c]
+        assert np.all(np.diff(chunk) > 0)
+        lo = 0 if c == 0 else limits[c - 1]
+        assert np.all((lens[chunk] > lo) | (c == 0)) and np.all(lens[chunk] <= limits[c])
+    assert L.ss_csr_schedule(indptr.ctypes.data, 0, order.ctypes.data, counts.ctypes.data) == B.SS_ESIZE
+    # a schedule whose class sizes do not add up to n_bins is refused before launch
+    bad = B.Csr(10, 5, 100, 50, 4096, 4096, 4096, 4096, (ctypes.c_int32 * B.SS_N_CLASSES)(1, 2, 0, 0, 0, 0, 0))
+    prof = B.Profile(*([4096] * 7))
+    good = B.Params(3.0, 5, 0, 0.0, 3.0, 0.0, 3.0, 3, 3)
+    ref = ctypes.byref
+    assert L.ss_sigma_clip(ctypes.c_void_p(4096), None, None, 1, ref(bad), ref(good), ref(prof), None) == B.SS_EINVAL
