@@ -110,10 +110,15 @@ __device__ inline bool clipped(float x, ClipBounds b) { return x > b.hi || x < b
 
 // Cut-off of pass k: the fixed value, or Chauvenet's value for the current
 // size (eq. chauvenet); <= 0 means nothing can be removed.
-__device__ inline double cutoff_for(double cutoff, double size) {
-    if (cutoff > 0.0) return cutoff;
+// (Out of line: the logarithm's constants would otherwise hold registers
+// across the whole pass loop of the kernels that inline the planner.)
+__device__ __attribute__((noinline)) double chauvenet_cutoff(double size) {
     constexpr double kSqrt2Pi = 2.5066282746310002;
     return size > kSqrt2Pi ? sqrt(2.0 * log(size / kSqrt2Pi)) : -1.0;
+}
+
+__device__ inline double cutoff_for(double cutoff, double size) {
+    return cutoff > 0.0 ? cutoff : chauvenet_cutoff(size);
 }
 
 // The running sums are decremented as members leave.  When the variance they
@@ -139,15 +144,15 @@ __device__ inline void add_member(double (&s)[NSUM], double w, double d, double 
     s[S_N] += 1.0;
 }
 
-// Work-group -> (frame, bin).  Work-groups are dispatched to the 8 XCDs
+// Work-group -> (frame, bin), or (group of fpi frames, bin).  Work-groups are dispatched to the 8 XCDs
 // round robin (work-group g runs on XCD g % 8), so work-group g is given the
 // item x * per + g / 8 of the frame-major list (frame, bin), x = g % 8: each
 // XCD walks a contiguous run of that list, and neighbouring bins of a frame,
 // whose rings share cache lines, run back to back on the same L2.  Returns
 // false for the padding work-groups beyond the list.
-__device__ inline bool block_item(const ClipArgs &a, int &f, int &bin) {
+__device__ inline bool block_item(const ClipArgs &a, int fpi, int &f, int &bin) {
     const uint32_t nb = uint32_t(a.launch_bins);
-    const uint32_t total = uint32_t(a.n_frames) * nb;
+    const uint32_t total = uint32_t((a.n_frames + fpi - 1) / fpi) * nb;
     const uint32_t per = (total + 7u) / 8u;
     const uint32_t g = blockIdx.x;
     const uint32_t item = (g % 8u) * per + g / 8u;
@@ -239,189 +244,317 @@ __device__ inline void load_state(const double *state, double (&s)[NSUM]) {
     for (int q = 0; q < NSUM; ++q) s[q] = state[q];
 }
 
-template <int BLOCK, int EPT>
-__global__ __launch_bounds__(BLOCK) void k_clip_regs(ClipArgs a) {
-    static_assert(EPT <= 64, "member flags live in one 64-bit word");
-    constexpr int NW = BLOCK / kWave;
-    __shared__ float w_s[EPT * BLOCK];
-    __shared__ double part[NSUM * NW];
-    __shared__ double tot[NSUM];
-    __shared__ double state[NSUM];
-    __shared__ PassCtl ctl;
+// Capacity (entries) of one wave's list of removed members, per frame and
+// round, in k_clip_regs.  It holds a full slot's worth (one entry per lane),
+// so every round makes progress.
+constexpr int kRemCap = kWave;
 
-    int f, bin;
-    if (!block_item(a, f, bin)) return;
+enum { R_W = 0, R_WD, R_W2, R_W2D, R_W2D2, NREM };
+
+typedef float float2v __attribute__((ext_vector_type(2)));
+
+__device__ inline void add_removed(double (&r)[NREM], double w, double d) {
+    const double w2 = w * w;
+    r[R_W] += w;
+    r[R_WD] += w * d;
+    r[R_W2] += w2;
+    r[R_W2D] += w2 * d;
+    r[R_W2D2] += w2 * d * d;
+}
+
+// Register-resident clip of one bin for FB frames at once.
+//
+// The work-group holds the row's weights in LDS (loaded once for all FB
+// frames) and each member's value in registers, slot e of thread t holding
+// entry e * BLOCK + t; a value is NaN when the entry is not, or no longer, a
+// member, so a clip compare leaves it alone.  The frames' reductions are
+// independent, so their latency chains overlap.
+//
+// A rejection pass: every wave compares its values against the frame's
+// bounds and packs the (weight, value) pairs of the members it removes into
+// its LDS list for that frame (ballot + prefix count); after a barrier,
+// wave f % NW sums the lists of frame f in a fixed order (deterministic),
+// takes the sums off the running state and plans the frame's next pass.  A wave
+// whose list fills up stops and asks for another round of the same pass.
+template <int BLOCK, int EPT, int FB, int WPE>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) void k_clip_regs(ClipArgs a) {
+    constexpr int NW = BLOCK / kWave;
+    constexpr int FPW = (FB + NW - 1) / NW;  // frames finished per wave
+    static_assert(FB >= 1 && BLOCK % kWave == 0, "whole waves, at least one frame");
+    constexpr int NP = (4 * FB > NSUM) ? 4 * FB : NSUM;
+    __shared__ float w_s[EPT * BLOCK];
+    __shared__ float2 rem_s[NW][FB][kRemCap];
+    __shared__ int cnt_s[NW][FB];
+    __shared__ int more_s[NW];
+    __shared__ double part[NP * NW];
+    __shared__ double tot[NP];
+    __shared__ double state[FB][NSUM];
+    __shared__ PassCtl ctl[FB];
+
+    int g, bin;
+    if (!block_item(a, FB, g, bin)) return;
+    const int f0 = g * FB;
+    const int nf = min(FB, a.n_frames - f0);
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const int wid = tid / kWave;
     int64_t start, end;
     row_bounds(a, bin, start, end);
     const int len = int(end - start);
-    const int32_t *__restrict__ idxs = a.indices + start;
-    const float *__restrict__ wts = a.weight + start;
-    const float *__restrict__ fr = a.frames + int64_t(f) * a.n_pix;
 
     if (len == 0) {
-        if (tid == 0) {
+        if (tid < nf) {
             const double z[NSUM] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-            write_profile(a, f, bin, z, Stats{0.0, 0.0, 0.0, 0.0, 0.0}, 0, a.max_iter > 0 ? 1 : 0);
+            write_profile(a, f0 + tid, bin, z, Stats{0.0, 0.0, 0.0, 0.0, 0.0}, 0, a.max_iter > 0 ? 1 : 0);
         }
         return;
     }
     const uint32_t last = uint32_t(a.n_pix - 1);
 
-    float v[EPT];
-    uint64_t act = 0;
-    double K = first_shift(a, fr, start, end);
-
-    // Buffer views of the row and of the frame: every load below is issued
-    // unconditionally (slots past the row end read 0 and are masked after)
-    // with one 32-bit offset register per slot and the slot's stride in a
-    // scalar.  The row's indices and weights are all requested before any
-    // gather, so a work-group waits for two memory round trips in total;
-    // the weights then live in LDS for the rest of the kernel.
-    const __amdgpu_buffer_rsrc_t ri = buffer_rsrc(idxs, uint32_t(len) * 4u);
-    const __amdgpu_buffer_rsrc_t rw = buffer_rsrc(wts, uint32_t(len) * 4u);
-    const __amdgpu_buffer_rsrc_t rf = buffer_rsrc(fr, uint32_t(a.n_pix) * 4u);
+    // Buffer views of the row and of the frames: every load below is issued
+    // unconditionally (slots past the row end, and frames past the batch,
+    // read 0 and are masked after) with one 32-bit offset register per slot
+    // and the slot's stride in a scalar.  A work-group waits for two memory
+    // round trips: the row's indices and weights, then the gathers.
+    const __amdgpu_buffer_rsrc_t ri = buffer_rsrc(a.indices + start, uint32_t(len) * 4u);
+    const __amdgpu_buffer_rsrc_t rw = buffer_rsrc(a.weight + start, uint32_t(len) * 4u);
+    __amdgpu_buffer_rsrc_t rf[FB];
+#pragma unroll
+    for (int f = 0; f < FB; ++f) {
+        const bool real = f < nf;
+        const float *fr = a.frames + (real ? int64_t(f0 + f) * a.n_pix : 0);
+        rf[f] = buffer_rsrc(fr, real ? uint32_t(a.n_pix) * 4u : 0u);
+    }
     const uint32_t tofs = uint32_t(tid) * 4u;
 
-    // sweep 1: gather, Omega, first mean
+    // Values are held in pairs: float64 operands need even-aligned register
+    // pairs, and single floats scattered over odd registers would leave the
+    // even ones unusable for them.
+    static_assert(EPT % 2 == 0, "values are held in pairs");
+    float2v vp[FB][EPT / 2];
+#define SS_V(f, e) vp[f][(e) >> 1][(e) & 1]
+    double K[FB];
+    // sweep 1: gather, Omega, first mean.  Register use peaks here, so the
+    // weights go to LDS as soon as they arrive, an entry's validity is taken
+    // into a bit mask before the gathers, and each index register is free
+    // once its gathers are issued.
     {
-        int32_t ix[EPT];
-        float wt[EPT];
+        uint64_t ok_entry = 0;
+        {
+            int32_t ix[EPT];
+            float wt[EPT];
 #pragma unroll
-        for (int e = 0; e < EPT; ++e) {
-            ix[e] = buffer_load_i32(ri, tofs, uint32_t(e * BLOCK) * 4u);
-            wt[e] = buffer_load_f32(rw, tofs, uint32_t(e * BLOCK) * 4u);
+            for (int e = 0; e < EPT; ++e) wt[e] = buffer_load_f32(rw, tofs, uint32_t(e * BLOCK) * 4u);
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) ix[e] = buffer_load_i32(ri, tofs, uint32_t(e * BLOCK) * 4u);
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) {
+                w_s[e * BLOCK + tid] = wt[e];
+                const bool ok = (e * BLOCK + tid < len) && wt[e] > 0.0f && uint32_t(ix[e]) <= last;
+                ok_entry |= uint64_t(ok) << e;
+            }
+#pragma unroll
+            for (int f = 0; f < FB; ++f)
+#pragma unroll
+                for (int e = 0; e < EPT; ++e) SS_V(f, e) = buffer_load_f32(rf[f], uint32_t(ix[e]) * 4u, 0u);
+        }
+        // (the weights are read back from LDS below, not kept in registers)
+        asm volatile("" ::: "memory");
+        // branch-free: a non-member enters the sums with weight and value 0
+        double t[3 * FB];
+        int n_ok[FB];
+#pragma unroll
+        for (int f = 0; f < FB; ++f) {
+            n_ok[f] = 0;
+            t[3 * f] = t[3 * f + 1] = 0.0;
         }
 #pragma unroll
-        for (int e = 0; e < EPT; ++e) v[e] = buffer_load_f32(rf, uint32_t(ix[e]) * 4u, 0u);
-#pragma unroll
-        for (int e = 0; e < EPT; ++e) w_s[e * BLOCK + tid] = wt[e];
-        double t[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
         for (int e = 0; e < EPT; ++e) {
-            const bool ok = (e * BLOCK + tid < len) && uint32_t(ix[e]) <= last && isfinite(v[e]) && wt[e] > 0.0f;
-            act |= uint64_t(ok) << e;
-            const double wd = ok ? double(wt[e]) : 0.0;
-            const double d = ok ? double(v[e]) - K : 0.0;
-            t[0] += wd;
-            t[1] += wd * d;
-            t[2] += wd * wd;
-            t[3] += ok ? 1.0 : 0.0;
+            const bool entry_ok = (uint32_t(ok_entry >> e) & 1u) != 0;
+            const float w = w_s[e * BLOCK + tid];
+#pragma unroll
+            for (int f = 0; f < FB; ++f) {
+                const float x = SS_V(f, e);
+                const bool ok = entry_ok && (f < nf) && __builtin_isfinite(x);
+                const float wz = ok ? w : 0.0f;
+                const float xz = ok ? x : 0.0f;
+                t[3 * f + 0] += double(wz);
+                t[3 * f + 1] = fma(double(wz), double(xz), t[3 * f + 1]);
+                n_ok[f] += ok ? 1 : 0;
+                SS_V(f, e) = ok ? x : __builtin_nanf("");
+            }
         }
-        block_sum<4, BLOCK>(t, part, tot);
-        K = (t[3] > 0.5 && t[0] > 0.0) ? K + t[1] / t[0] : 0.0;
-        if (tid == 0) {
-            state[S_W] = t[0];
-            state[S_W2] = t[2];
-            state[S_N] = t[3];
-            state[S_PV] = 0.0;
+#pragma unroll
+        for (int f = 0; f < FB; ++f) t[3 * f + 2] = double(n_ok[f]);
+        block_sum<3 * FB, BLOCK>(t, part, tot);
+#pragma unroll
+        for (int f = 0; f < FB; ++f) {
+            K[f] = (t[3 * f + 2] > 0.5 && t[3 * f] > 0.0) ? t[3 * f + 1] / t[3 * f] : 0.0;
+            if (tid == f) {
+                state[f][S_W] = t[3 * f];
+                state[f][S_N] = t[3 * f + 2];
+                state[f][S_PV] = 0.0;
+            }
         }
     }
+    // The float64 conversions of sweep 1 are not kept for sweep 2 (that
+    // would hold two more registers per member): the values pass through an
+    // empty asm statement, which the compiler cannot see through.
+#pragma unroll
+    for (int f = 0; f < FB; ++f)
+#pragma unroll
+        for (int e = 0; e < EPT / 2; ++e) asm volatile("" : "+v"(vp[f][e]));
     // sweep 2: deviations around the first mean (two-pass VV)
     {
-        double t[3] = {0.0, 0.0, 0.0};
+        double t[4 * FB];
+#pragma unroll
+        for (int q = 0; q < 4 * FB; ++q) t[q] = 0.0;
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
-            const bool ok = (act >> e) & 1u;
-            const double wd = ok ? double(w_s[e * BLOCK + tid]) : 0.0;
-            const double d = ok ? double(v[e]) - K : 0.0;
-            const double w2 = wd * wd;
-            t[0] += wd * d;
-            t[1] += w2 * d;
-            t[2] += w2 * d * d;
+            const float w = w_s[e * BLOCK + tid];
+#pragma unroll
+            for (int f = 0; f < FB; ++f) {
+                const float x = SS_V(f, e);
+                const bool ok = x == x;
+                const double wz = double(ok ? w : 0.0f);
+                const double d = double(ok ? x : 0.0f) - K[f];
+                const double wd = wz * d;
+                t[4 * f + 0] += wd;
+                t[4 * f + 1] = fma(wz, wz, t[4 * f + 1]);
+                t[4 * f + 2] = fma(wz, wd, t[4 * f + 2]);
+                t[4 * f + 3] = fma(wd, wd, t[4 * f + 3]);
+            }
         }
-        block_sum<3, BLOCK>(t, part, tot);
-        if (tid == 0) {
-            state[S_WD] = t[0];
-            state[S_W2D] = t[1];
-            state[S_W2D2] = t[2];
-            PassCtl c{0.0, 0.0, K, ClipBounds{0.0f, 0.0f}, 0, 0, 0, 0};
-            double sv[NSUM];
-            load_state(state, sv);
-            plan(a, sv, c, 0, false);
-            ctl = c;
+        block_sum<4 * FB, BLOCK>(t, part, tot);
+#pragma unroll
+        for (int f = 0; f < FB; ++f) {
+            if (tid == f) {
+                state[f][S_WD] = t[4 * f];
+                state[f][S_W2] = t[4 * f + 1];
+                state[f][S_W2D] = t[4 * f + 2];
+                state[f][S_W2D2] = t[4 * f + 3];
+                PassCtl c{0.0, 0.0, K[f], ClipBounds{0.0f, 0.0f}, 0, 0, 0, 0};
+                double sv[NSUM];
+                load_state(state[f], sv);
+                plan(a, sv, c, 0, false);
+                if (f >= nf) c.go = 0;
+                ctl[f] = c;
+            }
         }
     }
     __syncthreads();
 
     // rejection passes
-    for (int k = 0; ctl.go; ++k) {
-        if (ctl.refresh) {
+    for (int k = 0;; ++k) {
+        bool any = false;
+#pragma unroll
+        for (int f = 0; f < FB; ++f) any = any || ctl[f].go != 0;
+        if (!any) break;
+#pragma unroll
+        for (int f = 0; f < FB; ++f) {
+            if (!(ctl[f].go && ctl[f].refresh)) continue;
             // re-accumulate the surviving members around the current mean
-            const double Kn = ctl.mean;
+            const double Kn = ctl[f].mean;
             double t[NSUM] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
             for (int e = 0; e < EPT; ++e)
-                if ((act >> e) & 1u) add_member(t, double(w_s[e * BLOCK + tid]), double(v[e]) - Kn, 0.0);
+                if (SS_V(f, e) == SS_V(f, e)) add_member(t, double(w_s[e * BLOCK + tid]), double(SS_V(f, e)) - Kn, 0.0);
             block_sum<NSUM, BLOCK>(t, part, tot);
             if (tid == 0) {
                 t[S_N] = rint(t[S_N]);
 #pragma unroll
-                for (int q = 0; q < NSUM; ++q) state[q] = t[q];
-                PassCtl c = ctl;
+                for (int q = 0; q < NSUM; ++q) state[f][q] = t[q];
+                PassCtl c = ctl[f];
                 c.K = Kn;
                 plan(a, t, c, k, false);
-                ctl = c;
+                ctl[f] = c;
             }
             __syncthreads();
-            if (!ctl.go) break;
         }
-        const ClipBounds bnd = ctl.bounds;
-        const double Kc = ctl.K;
-        uint64_t rem = 0;
+        // running sums of the removed members of the frames this wave
+        // finishes (frames wid, wid + NW, ...), over the rounds of the pass
+        double r[FPW][NREM];
+        int n_removed[FPW];
 #pragma unroll
-        for (int e = 0; e < EPT; ++e)
-            if (((act >> e) & 1u) && clipped(v[e], bnd)) rem |= uint64_t(1) << e;
-        act &= ~rem;
-        // per-wave sums of the removed members; slots where no lane of the
-        // wave removed anything are skipped (wave-uniform test)
-        double r[NSUM] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-        if (__ballot(rem != 0) != 0) {
+        for (int j = 0; j < FPW; ++j) {
+            n_removed[j] = 0;
 #pragma unroll
-            for (int e = 0; e < EPT; ++e) {
-                const bool out = (rem >> e) & 1u;
-                if (__ballot(out) == 0) continue;
-                if (out) add_member(r, double(w_s[e * BLOCK + tid]), double(v[e]) - Kc, 0.0);
+            for (int q = 0; q < NREM; ++q) r[j][q] = 0.0;
+        }
+        for (;;) {
+            int more = 0;
+#pragma unroll
+            for (int f = 0; f < FB; ++f) {
+                int used = 0;
+                if (ctl[f].go) {
+                    const ClipBounds bnd = ctl[f].bounds;
+#pragma unroll
+                    for (int e = 0; e < EPT; ++e) {
+                        const bool out = clipped(SS_V(f, e), bnd);
+                        const uint64_t m = __ballot(out);
+                        if (m == 0) continue;
+                        const int cnt = __popcll(m);
+                        if (used + cnt > kRemCap) {
+                            more = 1;  // this slot waits for the next round
+                            continue;
+                        }
+                        if (out) {
+                            rem_s[wid][f][used + lanes_below(m)] = make_float2(w_s[e * BLOCK + tid], SS_V(f, e));
+                            SS_V(f, e) = __builtin_nanf("");
+                        }
+                        used = __builtin_amdgcn_readfirstlane(used + cnt);
+                    }
+                }
+                if (lane == 0) cnt_s[wid][f] = used;
             }
+            if (lane == 0) more_s[wid] = more;
+            __syncthreads();
+            int again = 0;
 #pragma unroll
-            for (int q = 0; q < NSUM; ++q) r[q] = wave_sum(r[q]);
-        }
-        if (lane == 0) {
+            for (int w = 0; w < NW; ++w) again |= more_s[w];
 #pragma unroll
-            for (int q = 0; q < NSUM; ++q) part[q * NW + wid] = r[q];
-        }
-        __syncthreads();
-        // wave 0 adds the per-wave sums (lane w reads wave w's), updates
-        // the running sums and plans the next pass
-        if (wid == 0) {
-            double x[NSUM];
+            for (int j = 0; j < FPW; ++j) {
+                const int f = wid + j * NW;
+                if (f >= FB || !ctl[f].go) continue;
+                const double Kc = ctl[f].K;
+                for (int w = 0; w < NW; ++w) {
+                    const int cnt = cnt_s[w][f];
+                    n_removed[j] += cnt;
+                    if (lane < cnt) {
+                        const float2 x = rem_s[w][f][lane];
+                        add_removed(r[j], double(x.x), double(x.y) - Kc);
+                    }
+                }
+                if (again) continue;
 #pragma unroll
-            for (int q = 0; q < NSUM; ++q) x[q] = lane < NW ? part[q * NW + lane] : 0.0;
+                for (int q = 0; q < NREM; ++q) r[j][q] = wave_sum_last(r[j][q]);
+                if (lane == kWave - 1) {
+                    double sv[NSUM];
+                    load_state(state[f], sv);
+                    sv[S_W] -= r[j][R_W];
+                    sv[S_WD] -= r[j][R_WD];
+                    sv[S_W2] -= r[j][R_W2];
+                    sv[S_W2D] -= r[j][R_W2D];
+                    sv[S_W2D2] -= r[j][R_W2D2];
+                    sv[S_N] -= double(n_removed[j]);
 #pragma unroll
-            for (int q = 0; q < NSUM; ++q) x[q] = wave_sum(x[q]);
-            if (lane == 0) {
-                double sv[NSUM];
-                load_state(state, sv);
-#pragma unroll
-                for (int q = 0; q < NSUM; ++q) sv[q] -= x[q];
-                sv[S_N] = rint(sv[S_N]);
-#pragma unroll
-                for (int q = 0; q < NSUM; ++q) state[q] = sv[q];
-                PassCtl c = ctl;
-                after_pass(c, x[S_N] >= 0.5);
-                if (c.go) plan(a, sv, c, k + 1, true);
-                ctl = c;
+                    for (int q = 0; q < NSUM; ++q) state[f][q] = sv[q];
+                    PassCtl c = ctl[f];
+                    after_pass(c, n_removed[j] > 0);
+                    if (c.go) plan(a, sv, c, k + 1, true);
+                    ctl[f] = c;
+                }
             }
+            __syncthreads();
+            if (!again) break;
         }
-        __syncthreads();
     }
-    if (tid == 0) {
+    if (tid < nf) {
         double sv[NSUM];
-        load_state(state, sv);
-        write_profile(a, f, bin, sv, stats_from(sv, ctl.K), ctl.n_iter, ctl.converged);
+        load_state(state[tid], sv);
+        write_profile(a, f0 + tid, bin, sv, stats_from(sv, ctl[tid].K), ctl[tid].n_iter, ctl[tid].converged);
     }
+#undef SS_V
 }
 
 // ---------------------------------------------------------------------------
@@ -434,7 +567,7 @@ __global__ __launch_bounds__(BLOCK) void k_clip_stream(ClipArgs a) {
     __shared__ ClipBounds hist[SS_MAX_ITER];
 
     int f, bin;
-    if (!block_item(a, f, bin)) return;
+    if (!block_item(a, 1, f, bin)) return;
     const int tid = threadIdx.x;
     int64_t start, end;
     row_bounds(a, bin, start, end);
@@ -535,26 +668,62 @@ __global__ __launch_bounds__(BLOCK) void k_clip_stream(ClipArgs a) {
 
 // ---------------------------------------------------------------------------
 
-template <int BLOCK, int EPT>
-void launch_regs(const ClipArgs &a, uint32_t grid, hipStream_t stream) {
-    k_clip_regs<BLOCK, EPT><<<dim3(grid), BLOCK, 0, stream>>>(a);
+template <int BLOCK, int EPT, int FB, int WPE>
+void launch_regs(const ClipArgs &a, hipStream_t stream) {
+    const int64_t groups = (int64_t(a.n_frames) + FB - 1) / FB;
+    k_clip_regs<BLOCK, EPT, FB, WPE><<<dim3(item_grid(groups * a.launch_bins)), BLOCK, 0, stream>>>(a);
 }
 
 template <int BLOCK>
-void launch_stream(const ClipArgs &a, uint32_t grid, hipStream_t stream) {
-    k_clip_stream<BLOCK><<<dim3(grid), BLOCK, 0, stream>>>(a);
+void launch_stream(const ClipArgs &a, hipStream_t stream) {
+    k_clip_stream<BLOCK><<<dim3(item_grid(int64_t(a.n_frames) * a.launch_bins)), BLOCK, 0, stream>>>(a);
 }
 
-// Work-group shape of row-length class c (rows up to ss_class_rows(c)).
-void launch_class(const ClipArgs &a, int c, uint32_t grid, hipStream_t stream) {
+// Work-group shape of row-length class c (rows up to ss_class_rows(c)):
+// threads, values per thread, frames per work-group and the waves per SIMD
+// the register budget is set for; batches use the first shape, single
+// frames the second.
+#ifndef SS_CLIP_C0
+#define SS_CLIP_C0 256, 4, 4, 4
+#endif
+#ifndef SS_CLIP_C1
+#define SS_CLIP_C1 256, 8, 4, 4
+#endif
+#ifndef SS_CLIP_C2
+#define SS_CLIP_C2 128, 32, 2, 4
+#endif
+#ifndef SS_CLIP_C3
+#define SS_CLIP_C3 256, 32, 1, 4
+#endif
+#ifndef SS_CLIP_C4
+#define SS_CLIP_C4 512, 32, 1, 4
+#endif
+#ifndef SS_CLIP_C5
+#define SS_CLIP_C5 1024, 24, 2, 4
+#endif
+#define SS_CLIP_C0_SINGLE 256, 4, 1, 5
+#define SS_CLIP_C1_SINGLE 256, 8, 1, 5
+#define SS_CLIP_C2_SINGLE 128, 32, 1, 4
+#define SS_CLIP_C3_SINGLE 256, 32, 1, 4
+#define SS_CLIP_C4_SINGLE 512, 32, 1, 4
+#define SS_CLIP_C5_SINGLE 1024, 24, 1, 4
+
+template <int ROWS, int BLOCK, int EPT, int FB, int WPE>
+void launch_shape(const ClipArgs &a, hipStream_t stream) {
+    static_assert(BLOCK * EPT >= ROWS, "a work-group holds the longest row of its class");
+    launch_regs<BLOCK, EPT, FB, WPE>(a, stream);
+}
+
+void launch_class(const ClipArgs &a, int c, hipStream_t stream) {
+    const bool batch = a.n_frames > 1;
     switch (c) {
-        case 0: launch_regs<256, 4>(a, grid, stream); break;
-        case 1: launch_regs<256, 8>(a, grid, stream); break;
-        case 2: launch_regs<256, 16>(a, grid, stream); break;
-        case 3: launch_regs<512, 16>(a, grid, stream); break;
-        case 4: launch_regs<1024, 16>(a, grid, stream); break;
-        case 5: launch_regs<1024, 24>(a, grid, stream); break;
-        default: launch_stream<1024>(a, grid, stream); break;
+        case 0: batch ? launch_shape<1024, SS_CLIP_C0>(a, stream) : launch_shape<1024, SS_CLIP_C0_SINGLE>(a, stream); break;
+        case 1: batch ? launch_shape<2048, SS_CLIP_C1>(a, stream) : launch_shape<2048, SS_CLIP_C1_SINGLE>(a, stream); break;
+        case 2: batch ? launch_shape<4096, SS_CLIP_C2>(a, stream) : launch_shape<4096, SS_CLIP_C2_SINGLE>(a, stream); break;
+        case 3: batch ? launch_shape<8192, SS_CLIP_C3>(a, stream) : launch_shape<8192, SS_CLIP_C3_SINGLE>(a, stream); break;
+        case 4: batch ? launch_shape<16384, SS_CLIP_C4>(a, stream) : launch_shape<16384, SS_CLIP_C4_SINGLE>(a, stream); break;
+        case 5: batch ? launch_shape<24576, SS_CLIP_C5>(a, stream) : launch_shape<24576, SS_CLIP_C5_SINGLE>(a, stream); break;
+        default: launch_stream<1024>(a, stream); break;
     }
 }
 
@@ -574,16 +743,15 @@ void dispatch(ClipArgs a, const ss_csr *csr, int n_frames, hipStream_t stream) {
         a.bin_order = nullptr;
         a.order_base = 0;
         a.launch_bins = a.n_bins;
-        const uint32_t grid = item_grid(int64_t(a.n_bins) * n_frames);
-        if (csr->max_row <= 4096) launch_stream<256>(a, grid, stream);
-        else launch_stream<1024>(a, grid, stream);
+        if (csr->max_row <= 4096) launch_stream<256>(a, stream);
+        else launch_stream<1024>(a, stream);
         return;
     }
     if (csr->bin_order == nullptr) {
         a.bin_order = nullptr;
         a.order_base = 0;
         a.launch_bins = a.n_bins;
-        launch_class(a, class_of(csr->max_row), item_grid(int64_t(a.n_bins) * n_frames), stream);
+        launch_class(a, class_of(csr->max_row), stream);
         return;
     }
     int32_t base = 0;
@@ -593,7 +761,7 @@ void dispatch(ClipArgs a, const ss_csr *csr, int n_frames, hipStream_t stream) {
         a.bin_order = csr->bin_order;
         a.order_base = base;
         a.launch_bins = cnt;
-        launch_class(a, c, item_grid(int64_t(cnt) * n_frames), stream);
+        launch_class(a, c, stream);
         base += cnt;
     }
 }

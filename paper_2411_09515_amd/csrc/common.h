@@ -29,17 +29,32 @@ __device__ inline double readlane(double x, int lane) {
                             __builtin_amdgcn_readlane(__double2loint(x), lane));
 }
 
-// Sum over the 64 lanes of a wavefront; every lane gets the same total.
-// Within each row of 16 lanes: quad_perm [1,0,3,2], quad_perm [2,3,0,1],
-// row_half_mirror and row_mirror leave the row's sum in every lane; the four
-// row sums are then added in a fixed order.
-__device__ inline double wave_sum(double x) {
+// Row broadcast (row_bcast:15 / row_bcast:31) into the rows of ROWS; lanes
+// of the other rows get 0.
+template <int CTRL, int ROWS>
+__device__ inline double dpp_bcast(double x) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, ROWS, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, ROWS, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes of a wavefront, left in lane 63.  Within each row of
+// 16 lanes quad_perm [1,0,3,2], quad_perm [2,3,0,1], row_half_mirror and
+// row_mirror leave the row's sum in every lane; row_bcast:15 then adds row 0
+// into row 1 and row 2 into row 3, and row_bcast:31 adds rows 0-1 into row
+// 3.  The order is fixed, so the result is reproducible.
+__device__ inline double wave_sum_last(double x) {
     x += dpp_move<0xB1>(x);
     x += dpp_move<0x4E>(x);
     x += dpp_move<0x141>(x);
     x += dpp_move<0x140>(x);
-    return (readlane(x, 0) + readlane(x, 16)) + (readlane(x, 32) + readlane(x, 48));
+    x += dpp_bcast<0x142, 0xA>(x);
+    x += dpp_bcast<0x143, 0xC>(x);
+    return x;
 }
+
+// The same total, given to every lane.
+__device__ inline double wave_sum(double x) { return readlane(wave_sum_last(x), kWave - 1); }
 
 __device__ inline int wave_sum(int v) {
 #pragma unroll
@@ -57,8 +72,8 @@ __device__ inline void block_sum(double (&v)[N], double *part, double *tot) {
     const int lane = threadIdx.x & (kWave - 1);
     const int wid = threadIdx.x / kWave;
 #pragma unroll
-    for (int k = 0; k < N; ++k) v[k] = wave_sum(v[k]);
-    if (lane == 0) {
+    for (int k = 0; k < N; ++k) v[k] = wave_sum_last(v[k]);
+    if (lane == kWave - 1) {
 #pragma unroll
         for (int k = 0; k < N; ++k) part[k * NW + wid] = v[k];
     }
