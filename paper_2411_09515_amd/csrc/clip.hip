@@ -7,7 +7,8 @@
 // so that mean = K + S_wd / S_w and, with delta = S_wd / S_w,
 //   VV = S_w2d2 - 2 delta S_w2d + delta^2 S_w2     (= sum omega^2 (v - mean)^2).
 // The first evaluation is a true two-pass: one sweep gives the mean, a second
-// sweep accumulates around K = that mean, so VV is well conditioned.  Every
+// sweep accumulates around K = that mean, so VV is well conditioned (the
+// register kernel does this per wave and merges the waves' sums exactly).  Every
 // rejection pass then accumulates only the members it removes and subtracts
 // them from the sums, so a pass costs one compare per member plus one
 // work-group reduction.
@@ -216,8 +217,18 @@ __device__ inline void after_pass(PassCtl &c, bool removed_any) {
 // Plan pass k_next from the running sums: a refresh of the sums when they
 // have lost precision, otherwise the next (mean, threshold), or stop.
 __device__ inline void plan(const ClipArgs &a, const double (&s)[NSUM], PassCtl &c, int k_next, bool allow_refresh) {
-    const Stats st = stats_from(s, c.K);
-    c.mean = st.mean;
+    // only the mean and the spread that clips are needed here (the other
+    // statistics are formed once, for the output)
+    double spread = 0.0;
+    c.mean = 0.0;
+    if (s[S_N] >= 0.5 && s[S_W] > 0.0) {
+        const double delta = s[S_WD] / s[S_W];
+        c.mean = c.K + delta;
+        double var = (a.model == SS_POISSON) ? s[S_PV]
+                                             : s[S_W2D2] - 2.0 * delta * s[S_W2D] + delta * delta * s[S_W2];
+        var = var > 0.0 ? var : 0.0;
+        spread = sqrt(var / s[S_W2]);
+    }
     c.refresh = 0;
     if (allow_refresh && needs_refresh(s)) {
         c.refresh = 1;
@@ -234,7 +245,7 @@ __device__ inline void plan(const ClipArgs &a, const double (&s)[NSUM], PassCtl 
         c.go = 0;
         return;
     }
-    c.thr = ncut * ((a.model == SS_POISSON) ? st.pstd : st.std);
+    c.thr = ncut * spread;
     c.bounds = clip_bounds(c.mean, c.thr);
     c.go = 1;
 }
@@ -250,6 +261,9 @@ __device__ inline void load_state(const double *state, double (&s)[NSUM]) {
 constexpr int kRemCap = kWave;
 
 enum { R_W = 0, R_WD, R_W2, R_W2D, R_W2D2, NREM };
+
+// Per-wave sums of the first evaluation (around the wave's own mean).
+enum { W_W = 0, W_WD, W_W2, W_W2D, W_W2D2, W_N, W_MEAN, NWSTAT };
 
 typedef float float2v __attribute__((ext_vector_type(2)));
 
@@ -281,14 +295,14 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) vo
     constexpr int NW = BLOCK / kWave;
     constexpr int FPW = (FB + NW - 1) / NW;  // frames finished per wave
     static_assert(FB >= 1 && BLOCK % kWave == 0, "whole waves, at least one frame");
-    constexpr int NP = (4 * FB > NSUM) ? 4 * FB : NSUM;
     __shared__ float w_s[EPT * BLOCK];
     __shared__ float2 rem_s[NW][FB][kRemCap];
     __shared__ int cnt_s[NW][FB];
     __shared__ int more_s[NW];
-    __shared__ double part[NP * NW];
-    __shared__ double tot[NP];
+    __shared__ double part[NSUM * NW];
+    __shared__ double tot[NSUM];
     __shared__ double state[FB][NSUM];
+    __shared__ double wstat[FB][NW][NWSTAT];
     __shared__ PassCtl ctl[FB];
 
     int g, bin;
@@ -334,7 +348,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) vo
     float2v vp[FB][EPT / 2];
 #define SS_V(f, e) vp[f][(e) >> 1][(e) & 1]
     double K[FB];
-    // sweep 1: gather, Omega, first mean.  Register use peaks here, so the
+    // sweep 1: gather, Omega, the wave's mean.  Register use peaks here, so the
     // weights go to LDS as soon as they arrive, an entry's validity is taken
     // into a bit mask before the gathers, and each index register is free
     // once its gathers are issued.
@@ -384,27 +398,31 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) vo
                 SS_V(f, e) = ok ? x : __builtin_nanf("");
             }
         }
-#pragma unroll
-        for (int f = 0; f < FB; ++f) t[3 * f + 2] = double(n_ok[f]);
-        block_sum<3 * FB, BLOCK>(t, part, tot);
+        // this wave's mean of each frame, known to all its lanes
 #pragma unroll
         for (int f = 0; f < FB; ++f) {
-            K[f] = (t[3 * f + 2] > 0.5 && t[3 * f] > 0.0) ? t[3 * f + 1] / t[3 * f] : 0.0;
-            if (tid == f) {
-                state[f][S_W] = t[3 * f];
-                state[f][S_N] = t[3 * f + 2];
-                state[f][S_PV] = 0.0;
+            t[3 * f + 0] = wave_sum(t[3 * f + 0]);
+            t[3 * f + 1] = wave_sum(t[3 * f + 1]);
+            t[3 * f + 2] = double(wave_sum(n_ok[f]));
+            K[f] = t[3 * f] > 0.0 ? t[3 * f + 1] / t[3 * f] : 0.0;
+            if (lane == kWave - 1) {
+                wstat[f][wid][W_W] = t[3 * f];
+                wstat[f][wid][W_N] = t[3 * f + 2];
+                wstat[f][wid][W_MEAN] = K[f];
             }
         }
     }
     // The float64 conversions of sweep 1 are not kept for sweep 2 (that
     // would hold two more registers per member): the values pass through an
-    // empty asm statement, which the compiler cannot see through.
+    // empty asm statement, which the compiler cannot see through, and no
+    // instruction is scheduled across this point (sweep 2's weight reads
+    // would otherwise be hoisted above the reductions, with their registers).
 #pragma unroll
     for (int f = 0; f < FB; ++f)
 #pragma unroll
         for (int e = 0; e < EPT / 2; ++e) asm volatile("" : "+v"(vp[f][e]));
-    // sweep 2: deviations around the first mean (two-pass VV)
+    __builtin_amdgcn_sched_barrier(0);
+    // sweep 2: deviations around the wave's mean (two-pass VV per wave)
     {
         double t[4 * FB];
 #pragma unroll
@@ -425,22 +443,51 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) vo
                 t[4 * f + 3] = fma(wd, wd, t[4 * f + 3]);
             }
         }
-        block_sum<4 * FB, BLOCK>(t, part, tot);
 #pragma unroll
-        for (int f = 0; f < FB; ++f) {
-            if (tid == f) {
-                state[f][S_WD] = t[4 * f];
-                state[f][S_W2] = t[4 * f + 1];
-                state[f][S_W2D] = t[4 * f + 2];
-                state[f][S_W2D2] = t[4 * f + 3];
-                PassCtl c{0.0, 0.0, K[f], ClipBounds{0.0f, 0.0f}, 0, 0, 0, 0};
-                double sv[NSUM];
-                load_state(state[f], sv);
-                plan(a, sv, c, 0, false);
-                if (f >= nf) c.go = 0;
-                ctl[f] = c;
+        for (int q = 0; q < 4 * FB; ++q) t[q] = wave_sum_last(t[q]);
+        if (lane == kWave - 1) {
+#pragma unroll
+            for (int f = 0; f < FB; ++f) {
+                wstat[f][wid][W_WD] = t[4 * f];
+                wstat[f][wid][W_W2] = t[4 * f + 1];
+                wstat[f][wid][W_W2D] = t[4 * f + 2];
+                wstat[f][wid][W_W2D2] = t[4 * f + 3];
             }
         }
+    }
+    __syncthreads();
+    // Merge the waves' sums, each taken around its own mean m_w, at the
+    // frame's mean K: with D = m_w - K a deviation around K is d + D, so
+    // S_wd gains D S_w, S_w2d gains D S_w2 and S_w2d2 gains
+    // 2 D S_w2d + D^2 S_w2 (exact algebra; every wave's own VV is two-pass).
+    if (tid < FB) {
+        const int f = tid;
+        double sw = 0.0, sv = 0.0;
+        // (not unrolled: one thread, and the table would fill its registers)
+#pragma unroll 1
+        for (int w = 0; w < NW; ++w) {
+            sw += wstat[f][w][W_W];
+            sv += wstat[f][w][W_W] * wstat[f][w][W_MEAN] + wstat[f][w][W_WD];
+        }
+        const double Kf = sw > 0.0 ? sv / sw : 0.0;
+        double st[NSUM] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll 1
+        for (int w = 0; w < NW; ++w) {
+            const double *x = wstat[f][w];
+            const double D = x[W_MEAN] - Kf;
+            st[S_W] += x[W_W];
+            st[S_WD] += x[W_WD] + D * x[W_W];
+            st[S_W2] += x[W_W2];
+            st[S_W2D] += x[W_W2D] + D * x[W_W2];
+            st[S_W2D2] += x[W_W2D2] + D * (2.0 * x[W_W2D] + D * x[W_W2]);
+            st[S_N] += x[W_N];
+        }
+#pragma unroll
+        for (int q = 0; q < NSUM; ++q) state[f][q] = st[q];
+        PassCtl c{0.0, 0.0, Kf, ClipBounds{0.0f, 0.0f}, 0, 0, 0, 0};
+        plan(a, st, c, 0, false);
+        if (f >= nf) c.go = 0;
+        ctl[f] = c;
     }
     __syncthreads();
 
@@ -690,7 +737,7 @@ void launch_stream(const ClipArgs &a, hipStream_t stream) {
 #define SS_CLIP_C1 256, 8, 4, 4
 #endif
 #ifndef SS_CLIP_C2
-#define SS_CLIP_C2 128, 32, 2, 4
+#define SS_CLIP_C2 256, 16, 2, 4
 #endif
 #ifndef SS_CLIP_C3
 #define SS_CLIP_C3 256, 32, 1, 4
