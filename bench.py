@@ -92,6 +92,32 @@ def algorithmic_bytes(geo, n_frames, n_pix_valid, n_kept, n_peaks):
     )
 
 
+STAGE_KERNELS = {
+    "correct": "ss_correct: k_correct_vec (+ k_fill_i64 clearing the invalid counts)",
+    "clip": "ss_sigma_clip: k_clip_regs, one launch per row-length class (6 launches)",
+    "classify": "ss_classify: k_profile_table, k_pixel_state, k_tile_counts, k_tile_scan, k_tile_write",
+}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "path_jungfrau4m_64frames_hbm_traffic.md")
+
+
+def measured_traffic(stage, n_frames):
+    """HBM bytes per launch of a stage from the committed counter summary
+    (FETCH_SIZE / WRITE_SIZE, scaled by a known-size copy), or None when the
+    summary is missing, was taken on another batch size, or the stage's
+    sources changed since."""
+    import hashlib
+    if n_frames != 64 or not os.path.exists(TRAFFIC_FILE):
+        return None
+    for line in open(TRAFFIC_FILE):
+        f = dict(kv.split("=", 1) for kv in line.split() if "=" in kv)
+        if line.strip().startswith("traffic ") and f.get("stage") == stage:
+            h = hashlib.sha256()
+            for src in f["sources"].split(","):
+                h.update(open(os.path.join(ROOT, src), "rb").read())
+            return int(f["bytes"]) if h.hexdigest()[:16] == f["sha256_16"] else None
+    return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -177,7 +203,7 @@ def main():
     one = api.Pipeline(geo, params, 1, pipe.pedestal, pipe.gain, kept_capacity=1 << 16, peak_capacity=1 << 12,
                        device=dev)
     lat = []
-    for i in range(args.latency_iters + 5):
+    for i in range(args.latency_iters + 5 if args.latency_iters > 0 else 0):
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         a.record(stream)
         one.run(raw[i % F: i % F + 1])
@@ -185,7 +211,10 @@ def main():
         b.synchronize()
         if i >= 5:
             lat.append(a.elapsed_time(b))
-    lat = np.array(lat if lat else [float("nan")])
+    latency = None
+    if lat:
+        latency = {"p50": round(float(np.percentile(lat, 50)), 4), "p99": round(float(np.percentile(lat, 99)), 4),
+                   "frames": len(lat)}
 
     line = {
         "metric": METRIC,
@@ -209,17 +238,21 @@ def main():
             "nnz": geo.nnz,
         },
         "stages_ms": {k: round(v, 4) for k, v in stage.items()},
-        "latency_ms_single_frame": {"p50": round(float(np.percentile(lat, 50)), 4),
-                                    "p99": round(float(np.percentile(lat, 99)), 4)},
+        "latency_ms_single_frame": latency,
         "roofline": {
-            "kernel": dom,
+            "kernel": STAGE_KERNELS[dom],
             "bound": "hbm",
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": measured_traffic(dom, F),
             "algorithmic_bytes_per_launch": alg[dom],
+            "launch_ms": round(stage[dom], 4),
+        },
+        "stages_roofline": {
+            k: {"algorithmic_bytes": alg[k], "achieved_gbs": round(alg[k] / (stage[k] * 1e-3) / 1e9, 1),
+                "traffic": measured_traffic(k, F)} for k in stage
         },
         "path_hbm_frac": round(sum(alg.values()) / (sum(stage.values()) * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "surrogate_vs_plain": None,
