@@ -307,6 +307,93 @@ int ss_peakfind(const float *frames, const uint8_t *mask, int32_t n_frames,
                 ss_peak *peaks, int64_t peak_capacity, int64_t *n_peaks,
                 void *workspace, size_t workspace_bytes, hipStream_t stream);
 
+/* ------------------------------------------------------------------------
+ * Learned clip surrogate.  Not in the paper: the paper's clip time grows
+ * with the number of passes (Sec. 2.4); a small network predicts each bin's
+ * converged clipped mean and std from the bin's unclipped statistics and a
+ * 16-point sketch of its standardised values, one verification pass checks
+ * the prediction, and the plain clip runs wherever the check fails.
+ *
+ * Features of a bin with n members, unclipped mean m0 and std s0 (azimuthal,
+ * eqs. avg, std2): x0 = log(1 + n), x1 = asinh(m0), x2 = asinh(s0),
+ * x(3+k) = #{v <= m0 + t_k s0} / n with t_k = -3.75 + 0.5 k, k = 0..15.
+ * Targets from a converged clip (mean mc, std sc): y0 = (mc - m0) / s0,
+ * y1 = log(sc / s0).  Network 19 -> 64 -> 64 -> 2, GELU (erf) on the hidden
+ * layers, float16 parameters, float32 arithmetic.  Parameters are one array
+ * of SS_MLP_PARAMS entries: W1 [SS_MLP_K1][64] (rows >= 19 zero), b1 [64],
+ * W2 [64][64], b2 [64], W3 [64][SS_MLP_OUT_PAD] (columns >= 2 zero),
+ * b3 [SS_MLP_OUT_PAD] (entries >= 2 zero), row-major, at SS_MLP_OFF_*.
+ * ---------------------------------------------------------------------- */
+#define SS_MLP_IN 19
+#define SS_MLP_HID 64
+#define SS_MLP_OUT 2
+#define SS_MLP_K1 32
+#define SS_MLP_OUT_PAD 16
+#define SS_MLP_OFF_W1 0
+#define SS_MLP_OFF_B1 2048
+#define SS_MLP_OFF_W2 2112
+#define SS_MLP_OFF_B2 6208
+#define SS_MLP_OFF_W3 6272
+#define SS_MLP_OFF_B3 7296
+#define SS_MLP_PARAMS 7312
+
+/* ss_clip_features -- the surrogate's inputs for every (frame, bin).
+ *   frames, norm: as ss_sigma_clip; mask must be NULL (masks are folded into
+ *     the CSR) and rows must not exceed ss_class_rows(SS_N_CLASSES - 2).
+ *   features [dev] float [n_frames][n_bins][SS_MLP_IN] (all 0 for an empty bin)
+ *   stats0 [dev] double [n_frames][n_bins][3]: n, m0, s0 (unclipped).
+ * Errors: SS_EINVAL (null pointers, a mask, a row too long), SS_ESIZE, SS_EHIP. */
+int ss_clip_features(const float *frames, const float *norm, const uint8_t *mask,
+                     int32_t n_frames, const ss_csr *csr, float *features, double *stats0,
+                     hipStream_t stream);
+
+/* ss_surrogate_targets -- training targets from ss_clip_features' stats0
+ * and a converged clip of the same frames (ref, [host] struct of device
+ * arrays, count entries each).  target [dev] float [count][2]; use [dev]
+ * uint8 [count] = 1 where n0 >= 2, s0 > 0, the clip converged with >= 2
+ * members and std > 0 (else the target is 0 and the sample unused). */
+int ss_surrogate_targets(const double *stats0, const ss_profile *ref, int64_t count,
+                         float *target, uint8_t *use, hipStream_t stream);
+
+/* ss_mlp_forward -- network outputs y [dev] float [n][2] for inputs
+ * x [dev] float [n][SS_MLP_IN]; w16 [dev] uint16 [SS_MLP_PARAMS] float16 bits. */
+int ss_mlp_forward(const uint16_t *w16, const float *x, int64_t n, float *y, hipStream_t stream);
+
+/* Workspace bytes ss_mlp_grad needs for n samples. */
+size_t ss_mlp_grad_workspace(int64_t n);
+
+/* ss_mlp_grad -- loss L = (1/n_used) sum over used samples of
+ * sum_o (y_o - target_o)^2 and its gradient with respect to the float16
+ * parameters, grad [dev] float [SS_MLP_PARAMS] (0 in the padding), loss
+ * [dev] float [1] (may be NULL).  use [dev] uint8 [n] or NULL (all used).
+ * Deterministic: fixed reduction order.  Errors: SS_EINVAL, SS_ESIZE
+ * (n <= 0, workspace too small), SS_EHIP. */
+int ss_mlp_grad(const uint16_t *w16, const float *x, const float *target, const uint8_t *use,
+                int64_t n, float *grad, float *loss, void *workspace, size_t workspace_bytes,
+                hipStream_t stream);
+
+/* ss_mlp_adam -- one Adam step (Kingma & Ba 2015; step counts from 1) on
+ * params / m / v [dev] float [SS_MLP_PARAMS], writing the float16 copy w16. */
+int ss_mlp_adam(float *params, float *m, float *v, const float *grad, int32_t step, float lr,
+                float beta1, float beta2, float eps, uint16_t *w16, hipStream_t stream);
+
+/* ss_sigma_clip_surrogate -- clipped profile with the surrogate: per (frame,
+ * bin) the network predicts (mean, std); then up to max_verify verification
+ * passes: E = members within cutoff x std of the mean, (mean, std) <- the
+ * statistics of E, accepted when E is exactly the set of members within
+ * cutoff x its own std of its own mean (a fixed point of the clip, so the
+ * statistics carry no residual), |E| >= 2 and its std > 0.  An accepted bin's
+ * profile holds E's statistics with n_iter = the verification passes used
+ * and converged = 1.  Every other bin runs the plain clip of ss_sigma_clip
+ * (params->max_iter passes).  Requires the azimuthal model, cutoff > 0,
+ * mask NULL, rows within ss_class_rows(SS_N_CLASSES - 2), w16 16-byte
+ * aligned and 1 <= max_verify <= SS_MAX_ITER.  accepted [dev] int32
+ * [n_frames][n_bins] or NULL.  Errors: SS_EINVAL, SS_ESIZE, SS_EHIP. */
+int ss_sigma_clip_surrogate(const float *frames, const float *norm, const uint8_t *mask,
+                            int32_t n_frames, const ss_csr *csr, const ss_params *params,
+                            const uint16_t *w16, int32_t max_verify, const ss_profile *out,
+                            int32_t *accepted, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -24,12 +24,14 @@ evaluates with every parameter rounded to float16 and float32-or-better
 arithmetic.  Loss: mean over the used samples of the squared error summed
 over the two outputs.
 
-Verified clip of one bin (cut-off c > 0):
-  E = {members with |v - mean_hat| <= c std_hat};  (m1, s1) = stats of E;
-  accept when |E| >= 2, s1 > 0, E equals {members with |v - m1| <= c s1}
-  (the set reproduces itself) and max(|m1 - mean_hat|, |s1 - std_hat|) / s1
-  <= max_residual.  An accepted bin reports the statistics of E with one
-  pass and converged = 1; any other bin falls back to the plain clip.
+Verified clip of one bin (cut-off c > 0), at most V verification passes:
+  (m0', s0') = (mean_hat, std_hat);  for k = 1 .. V:
+      E_k = {members with |v - m'_(k-1)| <= c s'_(k-1)};  (m'_k, s'_k) = stats of E_k;
+      accept when |E_k| >= 2, s'_k > 0 and E_k equals {members with
+      |v - m'_k| <= c s'_k} (the set reproduces itself: a fixed point of the
+      clip, so its statistics are exact, with no residual);
+  an accepted bin reports the statistics of E_k with n_iter = k and
+  converged = 1; any other bin falls back to the plain clip.
 """
 
 from __future__ import annotations
@@ -206,21 +208,25 @@ def adam(p, m, v, g, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
 
 # ---------------------------------------------------------------- verified clip
 
-def verified_bin(v, omega, mean_hat, std_hat, cutoff, max_residual):
-    """(accepted, E mask, stats of E) for one bin and one prediction."""
+def verified_bin(v, omega, mean_hat, std_hat, cutoff, max_verify):
+    """(accepted, passes, E mask, stats of E) for one bin and one prediction."""
     v = np.asarray(v, dtype=np.float64)
-    E = np.abs(v - mean_hat) <= cutoff * std_hat
-    m = S.moments(v[E], np.asarray(omega)[E])
-    if m["n"] < 2 or not (m["std"] > 0):
-        return False, E, m
-    again = np.abs(v - m["mean"]) <= cutoff * m["std"]
-    if not np.array_equal(again, E):
-        return False, E, m
-    res = max(abs(m["mean"] - mean_hat), abs(m["std"] - std_hat)) / m["std"]
-    return bool(res <= max_residual), E, m
+    omega = np.asarray(omega, dtype=np.float64)
+    mean, std = mean_hat, std_hat
+    E, m = None, None
+    for k in range(1, max_verify + 1):
+        E = np.abs(v - mean) <= cutoff * std
+        m = S.moments(v[E], omega[E])
+        if m["n"] < 2 or not (m["std"] > 0):
+            return False, k, E, m
+        again = np.abs(v - m["mean"]) <= cutoff * m["std"]
+        if np.array_equal(again, E):
+            return True, k, E, m
+        mean, std = m["mean"], m["std"]
+    return False, max_verify, E, m
 
 
-def surrogate_clip(frame, norm, csr, p, mask=None, cutoff=3.0, max_iter=32, max_residual=1e-3):
+def surrogate_clip(frame, norm, csr, p, mask=None, cutoff=3.0, max_iter=32, max_verify=2):
     """Profile of one frame from the verified surrogate, plain clip as fallback.
 
     Returns the dict of ``stats.sigma_clip`` plus ``accepted`` per bin.
@@ -240,10 +246,10 @@ def surrogate_clip(frame, norm, csr, p, mask=None, cutoff=3.0, max_iter=32, max_
         _, _, v, omega, _ = S.bin_members(frame, normf, csr, r, maskf)
         mean_hat = m0 + y[r, 0] * s0
         std_hat = s0 * math.exp(y[r, 1])
-        ok, E, m = verified_bin(v, omega, mean_hat, std_hat, cutoff, max_residual)
+        ok, k, E, m = verified_bin(v, omega, mean_hat, std_hat, cutoff, max_verify)
         if not ok:
             continue
         out["mean"][r], out["std"][r], out["sem"][r] = m["mean"], m["std"], m["sem"]
         out["sum_w"][r], out["n_members"][r] = m["Omega"], m["n"]
-        out["n_iter"][r], out["converged"][r], out["accepted"][r] = 1, 1, 1
+        out["n_iter"][r], out["converged"][r], out["accepted"][r] = k, 1, 1
     return out

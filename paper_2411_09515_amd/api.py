@@ -184,6 +184,117 @@ def integrate(frames, geom: Geometry, params: Params, out=None, norm=None, mask=
     return sigma_clip(frames, geom, params, out, norm, mask, integrate_only=True)
 
 
+# -- learned clip surrogate ---------------------------------------------------------------
+
+def clip_features(frames, geom: Geometry, norm=None):
+    """Surrogate inputs [F, nb, 19] (float32) and unclipped (n, mean, std) [F, nb, 3] (float64)."""
+    _need_device(frames, norm)
+    F = frames.shape[0]
+    feats = torch.empty((F, geom.n_bins, B.SS_MLP_IN), dtype=torch.float32, device=frames.device)
+    stats0 = torch.empty((F, geom.n_bins, 3), dtype=torch.float64, device=frames.device)
+    B.check("ss_clip_features", B.lib().ss_clip_features(_p(frames), _p(norm), None, F, ctypes.byref(geom.csr()),
+                                                         _p(feats), _p(stats0), _stream()))
+    return feats, stats0
+
+
+def surrogate_targets(stats0, profile):
+    """Training targets [n, 2] and use flags [n] from unclipped stats and a converged clip."""
+    n = stats0.numel() // 3
+    target = torch.empty((n, 2), dtype=torch.float32, device=stats0.device)
+    use = torch.empty(n, dtype=torch.uint8, device=stats0.device)
+    B.check("ss_surrogate_targets", B.lib().ss_surrogate_targets(_p(stats0), ctypes.byref(profile_c(profile)), n,
+                                                                 _p(target), _p(use), _stream()))
+    return target, use
+
+
+def init_mlp_params(seed=0):
+    """Seeded initial parameters in the library's layout: weights uniform in
+    +-1/sqrt(fan_in), biases and padding zero (float32, host)."""
+    rng = np.random.default_rng(seed)
+    p = np.zeros(B.SS_MLP_PARAMS, dtype=np.float32)
+    w1 = p[B.SS_MLP_OFF_W1:B.SS_MLP_OFF_B1].reshape(B.SS_MLP_K1, B.SS_MLP_HID)
+    w1[:B.SS_MLP_IN] = rng.uniform(-1, 1, (B.SS_MLP_IN, B.SS_MLP_HID)) / np.sqrt(B.SS_MLP_IN)
+    p[B.SS_MLP_OFF_W2:B.SS_MLP_OFF_B2] = (rng.uniform(-1, 1, (B.SS_MLP_HID, B.SS_MLP_HID)) /
+                                          np.sqrt(B.SS_MLP_HID)).reshape(-1)
+    w3 = p[B.SS_MLP_OFF_W3:B.SS_MLP_OFF_B3].reshape(B.SS_MLP_HID, B.SS_MLP_OUT_PAD)
+    w3[:, :B.SS_MLP_OUT] = rng.uniform(-1, 1, (B.SS_MLP_HID, B.SS_MLP_OUT)) / np.sqrt(B.SS_MLP_HID)
+    return p
+
+
+class Surrogate:
+    """The network's parameters on the device: float32 master copy with Adam
+    moments, and the float16 copy (as int16 bits) the kernels use."""
+
+    def __init__(self, params=None, device="cuda", seed=0):
+        p = init_mlp_params(seed) if params is None else np.ascontiguousarray(params, dtype=np.float32)
+        if p.size != B.SS_MLP_PARAMS:
+            raise ValueError(f"expected {B.SS_MLP_PARAMS} parameters")
+        self.params = torch.from_numpy(p.copy()).to(device)
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.w16 = torch.from_numpy(p.astype(np.float16).view(np.int16)).to(device)
+        self.grad = torch.zeros_like(self.params)
+        self.loss = torch.zeros(1, dtype=torch.float32, device=device)
+        self.step = 0
+        self._ws = None
+
+    def half_params(self) -> np.ndarray:
+        """The float16 parameters as float64 (host)."""
+        return self.w16.cpu().numpy().view(np.float16).astype(np.float64)
+
+    def forward(self, x):
+        _need_device(x)
+        n = x.shape[0]
+        y = torch.empty((n, B.SS_MLP_OUT), dtype=torch.float32, device=x.device)
+        B.check("ss_mlp_forward", B.lib().ss_mlp_forward(_p(self.w16), _p(x), n, _p(y), _stream()))
+        return y
+
+    def gradient(self, x, target, use=None):
+        """Loss and gradient (into self.loss / self.grad) on samples x [n, 19]."""
+        _need_device(x, target, use)
+        n = x.shape[0]
+        need = int(B.lib().ss_mlp_grad_workspace(n))
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = torch.empty(need, dtype=torch.uint8, device=x.device)
+        B.check("ss_mlp_grad", B.lib().ss_mlp_grad(_p(self.w16), _p(x), _p(target), _p(use), n, _p(self.grad),
+                                                   _p(self.loss), _p(self._ws), self._ws.numel(), _stream()))
+        return self.loss, self.grad
+
+    def adam(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        self.step += 1
+        B.check("ss_mlp_adam", B.lib().ss_mlp_adam(_p(self.params), _p(self.m), _p(self.v), _p(self.grad), self.step,
+                                                   lr, beta1, beta2, eps, _p(self.w16), _stream()))
+
+    def train(self, x, target, use=None, steps=1000, batch=8192, lr=2e-3, seed=0, log_every=0):
+        """Adam on shuffled minibatches of the samples; returns the loss history (host floats,
+        one per logged step)."""
+        n = x.shape[0]
+        g = torch.Generator(device="cpu").manual_seed(seed)
+        hist = []
+        for s in range(steps):
+            idx = torch.randint(0, n, (min(batch, n),), generator=g).to(x.device)
+            self.gradient(x[idx].contiguous(), target[idx].contiguous(),
+                          None if use is None else use[idx].contiguous())
+            self.adam(lr=lr)
+            if log_every and (s % log_every == 0 or s == steps - 1):
+                hist.append(float(self.loss.item()))
+        return hist
+
+
+def sigma_clip_surrogate(frames, geom: Geometry, params: Params, model: Surrogate, out=None, max_verify=2,
+                         accepted=None, norm=None):
+    """Clipped profile with the verified surrogate first, the plain clip elsewhere."""
+    _need_device(frames, norm, accepted)
+    F = frames.shape[0]
+    if out is None:
+        out = new_profile(F, geom.n_bins, frames.device)
+    B.check("ss_sigma_clip_surrogate",
+            B.lib().ss_sigma_clip_surrogate(_p(frames), _p(norm), None, F, ctypes.byref(geom.csr()),
+                                            ctypes.byref(params.c()), _p(model.w16), max_verify,
+                                            ctypes.byref(profile_c(out)), _p(accepted), _stream()))
+    return out
+
+
 # -- classification ----------------------------------------------------------------------
 
 def workspace_bytes(n_frames, n_pix, n_bins) -> int:

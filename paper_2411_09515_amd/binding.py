@@ -23,12 +23,19 @@ SS_MAX_BINS = 4094
 SS_MAX_ITER = 32
 SS_MAX_PATCH = 15
 SS_N_CLASSES = 7
+SS_MLP_IN, SS_MLP_HID, SS_MLP_OUT = 19, 64, 2
+SS_MLP_K1, SS_MLP_OUT_PAD = 32, 16
+SS_MLP_OFF_W1, SS_MLP_OFF_B1, SS_MLP_OFF_W2 = 0, 2048, 2112
+SS_MLP_OFF_B2, SS_MLP_OFF_W3, SS_MLP_OFF_B3 = 6208, 6272, 7296
+SS_MLP_PARAMS = 7312
 
 EXPORTED = (
     "ss_strerror", "ss_version", "ss_build_csr", "ss_csr_schedule", "ss_class_rows", "ss_radial_coords",
     "ss_correct",
     "ss_integrate", "ss_sigma_clip", "ss_classify_workspace", "ss_classify",
     "ss_compress", "ss_peakfind",
+    "ss_clip_features", "ss_surrogate_targets", "ss_mlp_forward", "ss_mlp_grad_workspace", "ss_mlp_grad",
+    "ss_mlp_adam", "ss_sigma_clip_surrogate",
 )
 
 
@@ -111,6 +118,21 @@ def lib():
         L.ss_peakfind.restype = ctypes.c_int
         L.ss_peakfind.argtypes = [vp, vp, i32, i32, i32, P(Radial), P(Profile), P(Params), vp, i64, vp,
                                   vp, sz, vp]
+        f32 = ctypes.c_float
+        L.ss_clip_features.restype = ctypes.c_int
+        L.ss_clip_features.argtypes = [vp, vp, vp, i32, P(Csr), vp, vp, vp]
+        L.ss_surrogate_targets.restype = ctypes.c_int
+        L.ss_surrogate_targets.argtypes = [vp, P(Profile), i64, vp, vp, vp]
+        L.ss_mlp_forward.restype = ctypes.c_int
+        L.ss_mlp_forward.argtypes = [vp, vp, i64, vp, vp]
+        L.ss_mlp_grad_workspace.restype = sz
+        L.ss_mlp_grad_workspace.argtypes = [i64]
+        L.ss_mlp_grad.restype = ctypes.c_int
+        L.ss_mlp_grad.argtypes = [vp, vp, vp, vp, i64, vp, vp, vp, sz, vp]
+        L.ss_mlp_adam.restype = ctypes.c_int
+        L.ss_mlp_adam.argtypes = [vp, vp, vp, vp, i32, f32, f32, f32, f32, vp, vp]
+        L.ss_sigma_clip_surrogate.restype = ctypes.c_int
+        L.ss_sigma_clip_surrogate.argtypes = [vp, vp, vp, i32, P(Csr), P(Params), vp, i32, P(Profile), vp, vp]
         _lib = L
     return _lib
 

@@ -17,7 +17,7 @@ OUT_DIR = os.path.join(PKG, "_lib")
 LIB = os.path.join(OUT_DIR, "libsigsep.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["correct.hip", "clip.hip", "classify.hip", "geometry.cpp"]
+SOURCES = ["correct.hip", "clip.hip", "classify.hip", "mlp.hip", "geometry.cpp"]
 HEADERS = ["common.h"]
 
 # Packed-FP32 instructions are kept out of the device code.

@@ -22,6 +22,8 @@
 //   It serves the Poisson and hybrid models, an extra mask and rows of any
 //   length.
 
+#include <hip/hip_fp16.h>
+
 #include <cmath>
 
 #include "common.h"
@@ -56,7 +58,17 @@ struct ClipArgs {
     int32_t *n_members;
     int32_t *n_iter;
     int32_t *converged;
+    // surrogate (register kernel only)
+    float *features;        // [F][nb][SS_MLP_IN], features mode
+    double *stats0;         // [F][nb][3], features mode
+    const uint16_t *w16;    // [SS_MLP_PARAMS] float16 bits, surrogate mode
+    int32_t max_verify;     // verification passes, surrogate mode
+    int32_t *accepted;      // [F][nb] or null, surrogate mode
 };
+
+// What k_clip_regs computes: the clipped profile, the surrogate's features
+// only, or the clipped profile with the verified surrogate first.
+enum { MODE_CLIP = 0, MODE_FEATURES = 1, MODE_SURROGATE = 2 };
 
 struct Stats {
     double mean, std, sem, pstd, psem;
@@ -290,11 +302,277 @@ __device__ inline void add_removed(double (&r)[NREM], double w, double d) {
 // wave f % NW sums the lists of frame f in a fixed order (deterministic),
 // takes the sums off the running state and plans the frame's next pass.  A wave
 // whose list fills up stops and asks for another round of the same pass.
-template <int BLOCK, int EPT, int FB, int WPE>
+// Per-frame surrogate state, in LDS.
+struct Surrogate {
+    double n0, m0, s0;          // unclipped statistics
+    double mean_hat, std_hat;   // the network's prediction
+    double mean, std, sem, sum_w, n;  // statistics of E
+    float lo, hi;               // E = members with lo <= v <= hi
+    ClipBounds again;           // clip bounds of E's own statistics
+    int on;                     // a real frame with members
+    int verify;                 // a prediction to verify
+    int accepted;
+};
+
+__device__ inline float half_to_float(uint16_t h) { return __half2float(__ushort_as_half(h)); }
+
+__device__ inline float gelu(float u) { return 0.5f * u * (1.0f + erff(u * 0.70710678118654752f)); }
+
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+#define SS_V(f, e) vp[f][(e) >> 1][(e) & 1]
+
+// The surrogate stage of k_clip_regs, after the first evaluation: the
+// 16-point sketch and the features; in surrogate mode also the network's
+// prediction (wave 0, one hidden unit per lane) and up to max_verify
+// verification passes (the statistics of the member set E the current
+// estimate selects, and the check that E reproduces itself).  Accepted frames
+// get their profile written here and take no clipping pass.
+// Returns true when the work-group is done (features mode).
+template <int BLOCK, int EPT, int FB, int MODE>
+__device__ inline bool surrogate_stage(const ClipArgs &a, float2v (&vp)[FB][EPT / 2], const float *w_s,
+                                       uint32_t *hist, float (*sk_s)[16], float (*feat_s)[SS_MLP_IN],
+                                       Surrogate *sur_s, const uint16_t *wts_s, float *h1_s, int *bad_s,
+                                       double *wstat, PassCtl *ctl, int f0, int nf, int bin) {
+    constexpr int NW = BLOCK / kWave;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
+
+    // sketch: member v goes to bucket j = #{k : v > b_k}; then #{v <= b_k} is
+    // the sum of buckets 0..k (the bounds do not decrease)
+#pragma unroll
+    for (int f = 0; f < FB; ++f)
+        if (lane < 17) hist[(f * NW + wid) * 17 + lane] = 0u;
+    wave_sync();
+#pragma unroll
+    for (int f = 0; f < FB; ++f) {
+        if (!sur_s[f].on) continue;
+        float b[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) b[k] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(sk_s[f][k])));
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            const float x = SS_V(f, e);
+            if (x == x) {
+                uint32_t j = 0;
+#pragma unroll
+                for (int k = 0; k < 16; ++k) j += x > b[k] ? 1u : 0u;
+                atomicAdd(&hist[(f * NW + wid) * 17 + j], 1u);
+            }
+        }
+    }
+    __syncthreads();
+    if (tid < FB) {
+        const int f = tid;
+        const Surrogate u = sur_s[f];
+        float x[SS_MLP_IN];
+#pragma unroll
+        for (int q = 0; q < SS_MLP_IN; ++q) x[q] = 0.0f;
+        if (u.on) {
+            x[0] = float(log1p(u.n0));
+            x[1] = float(asinh(u.m0));
+            x[2] = float(asinh(u.s0));
+            uint32_t cum = 0;
+            for (int k = 0; k < 16; ++k) {
+                for (int w = 0; w < NW; ++w) cum += hist[(f * NW + w) * 17 + k];
+                x[3 + k] = float(double(cum) / u.n0);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < SS_MLP_IN; ++q) feat_s[f][q] = x[q];
+        if (MODE == MODE_FEATURES && f < nf) {
+            const int64_t o = int64_t(f0 + f) * a.n_bins + bin;
+#pragma unroll
+            for (int q = 0; q < SS_MLP_IN; ++q) a.features[o * SS_MLP_IN + q] = x[q];
+            a.stats0[o * 3] = u.n0;
+            a.stats0[o * 3 + 1] = u.on ? u.m0 : 0.0;
+            a.stats0[o * 3 + 2] = u.on ? u.s0 : 0.0;
+        }
+    }
+    if constexpr (MODE == MODE_FEATURES) return true;
+    __syncthreads();
+
+    // the network, on wave 0: lane j is hidden unit j of both layers
+    if (wid == 0) {
+        float z[FB];
+#pragma unroll
+        for (int f = 0; f < FB; ++f) z[f] = half_to_float(wts_s[SS_MLP_OFF_B1 + lane]);
+#pragma unroll 1
+        for (int i = 0; i < SS_MLP_IN; ++i) {
+            const float w = half_to_float(wts_s[SS_MLP_OFF_W1 + i * SS_MLP_HID + lane]);
+#pragma unroll
+            for (int f = 0; f < FB; ++f) z[f] = fmaf(feat_s[f][i], w, z[f]);
+        }
+#pragma unroll
+        for (int f = 0; f < FB; ++f) h1_s[f * SS_MLP_HID + lane] = gelu(z[f]);
+        wave_sync();
+#pragma unroll
+        for (int f = 0; f < FB; ++f) z[f] = half_to_float(wts_s[SS_MLP_OFF_B2 + lane]);
+#pragma unroll 2
+        for (int i = 0; i < SS_MLP_HID; ++i) {
+            const float w = half_to_float(wts_s[SS_MLP_OFF_W2 + i * SS_MLP_HID + lane]);
+#pragma unroll
+            for (int f = 0; f < FB; ++f) z[f] = fmaf(h1_s[f * SS_MLP_HID + i], w, z[f]);
+        }
+        const float w30 = half_to_float(wts_s[SS_MLP_OFF_W3 + lane * SS_MLP_OUT_PAD]);
+        const float w31 = half_to_float(wts_s[SS_MLP_OFF_W3 + lane * SS_MLP_OUT_PAD + 1]);
+        const float b30 = half_to_float(wts_s[SS_MLP_OFF_B3]);
+        const float b31 = half_to_float(wts_s[SS_MLP_OFF_B3 + 1]);
+#pragma unroll
+        for (int f = 0; f < FB; ++f) {
+            const float h2 = gelu(z[f]);
+            const double y0 = wave_sum(double(h2 * w30)) + double(b30);
+            const double y1 = wave_sum(double(h2 * w31)) + double(b31);
+            if (lane == 0) {
+                Surrogate u = sur_s[f];
+                u.verify = u.on && u.n0 >= 2.0 && u.s0 > 0.0;
+                u.mean_hat = u.m0 + y0 * u.s0;
+                u.std_hat = u.s0 * exp(y1);
+                const double thr = a.cutoff * u.std_hat;
+                // |v - mean_hat| <= thr exactly when lo <= v <= hi
+                u.lo = __double2float_ru(u.mean_hat - thr);
+                u.hi = __double2float_rd(u.mean_hat + thr);
+                u.accepted = 0;
+                sur_s[f] = u;
+            }
+        }
+    }
+    __syncthreads();
+
+    // verification passes: E from the current (mean, std), E's statistics
+    // (shifted by that mean), then whether E reproduces itself
+    for (int k = 1; k <= a.max_verify; ++k) {
+        {
+            double t[FB][6];
+#pragma unroll
+            for (int f = 0; f < FB; ++f) {
+#pragma unroll
+                for (int q = 0; q < 6; ++q) t[f][q] = 0.0;
+                if (!sur_s[f].verify) continue;
+                const float lo = sur_s[f].lo, hi = sur_s[f].hi;
+                const double Kf = sur_s[f].mean_hat;
+#pragma unroll
+                for (int e = 0; e < EPT; ++e) {
+                    const float x = SS_V(f, e);
+                    const float w = w_s[e * BLOCK + tid];
+                    const bool in = x >= lo && x <= hi;
+                    const double wz = double(in ? w : 0.0f);
+                    const double d = double(in ? x : 0.0f) - Kf;
+                    const double wd = wz * d;
+                    t[f][0] += wz;
+                    t[f][1] += wd;
+                    t[f][2] = fma(wz, wz, t[f][2]);
+                    t[f][3] = fma(wz, wd, t[f][3]);
+                    t[f][4] = fma(wd, wd, t[f][4]);
+                    t[f][5] += in ? 1.0 : 0.0;
+                }
+#pragma unroll
+                for (int q = 0; q < 6; ++q) t[f][q] = wave_sum_last(t[f][q]);
+                if (lane == kWave - 1) {
+#pragma unroll
+                    for (int q = 0; q < 6; ++q) wstat[(f * NW + wid) * NWSTAT + q] = t[f][q];
+                }
+            }
+        }
+        __syncthreads();
+        if (tid < FB && sur_s[tid].verify) {
+            const int f = tid;
+            Surrogate u = sur_s[f];
+            double sm[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll 1
+            for (int w = 0; w < NW; ++w)
+#pragma unroll
+                for (int q = 0; q < 6; ++q) sm[q] += wstat[(f * NW + w) * NWSTAT + q];
+            if (sm[5] >= 1.5 && sm[0] > 0.0) {
+                const double delta = sm[1] / sm[0];
+                double vv = sm[4] - 2.0 * delta * sm[3] + delta * delta * sm[2];
+                vv = vv > 0.0 ? vv : 0.0;
+                u.mean = u.mean_hat + delta;
+                u.std = sqrt(vv / sm[2]);
+                u.sem = sqrt(vv) / sm[0];
+                u.sum_w = sm[0];
+                u.n = sm[5];
+                u.again = clip_bounds(u.mean, a.cutoff * u.std);
+                u.verify = u.std > 0.0;
+            } else {
+                u.verify = 0;
+            }
+            sur_s[f] = u;
+        }
+        __syncthreads();
+        // E must be exactly the members within the clip bounds of E's statistics
+#pragma unroll
+        for (int f = 0; f < FB; ++f) {
+            if (!sur_s[f].verify) continue;
+            const float lo = sur_s[f].lo, hi = sur_s[f].hi;
+            const ClipBounds again = sur_s[f].again;
+            bool bad = false;
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) {
+                const float x = SS_V(f, e);
+                const bool in_e = x >= lo && x <= hi;
+                const bool in_again = (x == x) && !clipped(x, again);
+                bad = bad || (in_e != in_again);
+            }
+            const uint64_t m = __ballot(bad);
+            if (lane == 0) bad_s[f * NW + wid] = m != 0;
+        }
+        __syncthreads();
+        if (tid < FB && sur_s[tid].verify) {
+            const int f = tid;
+            Surrogate u = sur_s[f];
+            bool bad = false;
+            for (int w = 0; w < NW; ++w) bad = bad || bad_s[f * NW + w];
+            if (!bad) {
+                u.accepted = 1;
+                u.verify = 0;
+                if (f < nf) {
+                    const int64_t o = int64_t(f0 + f) * a.n_bins + bin;
+                    a.mean[o] = u.mean;
+                    a.std[o] = u.std;
+                    a.sem[o] = u.sem;
+                    a.sum_w[o] = u.sum_w;
+                    a.n_members[o] = int32_t(u.n);
+                    a.n_iter[o] = k;
+                    a.converged[o] = 1;
+                }
+                ctl[f].go = 0;
+            } else {
+                // the next E: the members within E's own bounds
+                u.lo = u.again.lo;
+                u.hi = u.again.hi;
+                u.mean_hat = u.mean;
+                u.verify = k < a.max_verify;
+            }
+            sur_s[f] = u;
+        }
+        __syncthreads();
+        bool any = false;
+#pragma unroll
+        for (int f = 0; f < FB; ++f) any = any || sur_s[f].verify;
+        if (!any) break;
+    }
+    if (tid < nf && a.accepted) a.accepted[int64_t(f0 + tid) * a.n_bins + bin] = sur_s[tid].accepted;
+    return false;
+}
+
+template <int BLOCK, int EPT, int FB, int WPE, int MODE>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) void k_clip_regs(ClipArgs a) {
     constexpr int NW = BLOCK / kWave;
     constexpr int FPW = (FB + NW - 1) / NW;  // frames finished per wave
     static_assert(FB >= 1 && BLOCK % kWave == 0, "whole waves, at least one frame");
+    constexpr bool SKETCH = MODE != MODE_CLIP;
+    constexpr bool SUR = MODE == MODE_SURROGATE;
+    __shared__ uint32_t hist[SKETCH ? FB : 1][SKETCH ? NW : 1][17];
+    __shared__ float sk_s[FB][16];          // sketch bounds
+    __shared__ float feat_s[FB][SS_MLP_IN];
+    __shared__ Surrogate sur_s[FB];
+    __shared__ uint16_t wts_s[SUR ? SS_MLP_PARAMS : 2];
+    __shared__ float h1_s[SUR ? FB : 1][SS_MLP_HID];
+    __shared__ int bad_s[SUR ? FB : 1][SUR ? NW : 1];
     __shared__ float w_s[EPT * BLOCK];
     __shared__ float2 rem_s[NW][FB][kRemCap];
     __shared__ int cnt_s[NW][FB];
@@ -318,8 +596,15 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) vo
 
     if (len == 0) {
         if (tid < nf) {
-            const double z[NSUM] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-            write_profile(a, f0 + tid, bin, z, Stats{0.0, 0.0, 0.0, 0.0, 0.0}, 0, a.max_iter > 0 ? 1 : 0);
+            const int64_t o = int64_t(f0 + tid) * a.n_bins + bin;
+            if constexpr (MODE == MODE_FEATURES) {
+                for (int q = 0; q < SS_MLP_IN; ++q) a.features[o * SS_MLP_IN + q] = 0.0f;
+                for (int q = 0; q < 3; ++q) a.stats0[o * 3 + q] = 0.0;
+            } else {
+                const double z[NSUM] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+                write_profile(a, f0 + tid, bin, z, Stats{0.0, 0.0, 0.0, 0.0, 0.0}, 0, a.max_iter > 0 ? 1 : 0);
+                if (SUR && a.accepted) a.accepted[o] = 0;
+            }
         }
         return;
     }
@@ -346,7 +631,6 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) vo
     // even ones unusable for them.
     static_assert(EPT % 2 == 0, "values are held in pairs");
     float2v vp[FB][EPT / 2];
-#define SS_V(f, e) vp[f][(e) >> 1][(e) & 1]
     double K[FB];
     // sweep 1: gather, Omega, the wave's mean.  Register use peaks here, so the
     // weights go to LDS as soon as they arrive, an entry's validity is taken
@@ -371,6 +655,12 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) vo
             for (int f = 0; f < FB; ++f)
 #pragma unroll
                 for (int e = 0; e < EPT; ++e) SS_V(f, e) = buffer_load_f32(rf[f], uint32_t(ix[e]) * 4u, 0u);
+        }
+        if constexpr (SUR) {
+            // the network's parameters, while the gathers are in flight
+            const uint4 *src = reinterpret_cast<const uint4 *>(a.w16);
+            uint4 *dst = reinterpret_cast<uint4 *>(wts_s);
+            for (int i = tid; i < SS_MLP_PARAMS / 8; i += BLOCK) dst[i] = src[i];
         }
         // (the weights are read back from LDS below, not kept in registers)
         asm volatile("" ::: "memory");
@@ -488,8 +778,25 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) vo
         plan(a, st, c, 0, false);
         if (f >= nf) c.go = 0;
         ctl[f] = c;
+        if constexpr (SKETCH) {
+            const Stats s0 = stats_from(st, Kf);
+            Surrogate u{};
+            u.n0 = st[S_N];
+            u.m0 = s0.mean;
+            u.s0 = s0.std;
+            u.on = f < nf && st[S_N] >= 0.5;
+            sur_s[f] = u;
+            // v <= m0 + t s0 exactly when v <= RD32(m0 + t s0)
+#pragma unroll
+            for (int k = 0; k < 16; ++k) sk_s[f][k] = __double2float_rd(s0.mean + (-3.75 + 0.5 * k) * s0.std);
+        }
     }
     __syncthreads();
+    if constexpr (SKETCH) {
+        if (surrogate_stage<BLOCK, EPT, FB, MODE>(a, vp, w_s, &hist[0][0][0], sk_s, feat_s, sur_s, wts_s, &h1_s[0][0],
+                                                  &bad_s[0][0], &wstat[0][0][0], ctl, f0, nf, bin))
+            return;
+    }
 
     // rejection passes
     for (int k = 0;; ++k) {
@@ -596,13 +903,13 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) vo
             if (!again) break;
         }
     }
-    if (tid < nf) {
+    if (tid < nf && !(SUR && sur_s[tid].accepted)) {
         double sv[NSUM];
         load_state(state[tid], sv);
         write_profile(a, f0 + tid, bin, sv, stats_from(sv, ctl[tid].K), ctl[tid].n_iter, ctl[tid].converged);
     }
-#undef SS_V
 }
+#undef SS_V
 
 // ---------------------------------------------------------------------------
 
@@ -715,10 +1022,10 @@ __global__ __launch_bounds__(BLOCK) void k_clip_stream(ClipArgs a) {
 
 // ---------------------------------------------------------------------------
 
-template <int BLOCK, int EPT, int FB, int WPE>
+template <int BLOCK, int EPT, int FB, int WPE, int MODE>
 void launch_regs(const ClipArgs &a, hipStream_t stream) {
     const int64_t groups = (int64_t(a.n_frames) + FB - 1) / FB;
-    k_clip_regs<BLOCK, EPT, FB, WPE><<<dim3(item_grid(groups * a.launch_bins)), BLOCK, 0, stream>>>(a);
+    k_clip_regs<BLOCK, EPT, FB, WPE, MODE><<<dim3(item_grid(groups * a.launch_bins)), BLOCK, 0, stream>>>(a);
 }
 
 template <int BLOCK>
@@ -756,20 +1063,26 @@ void launch_stream(const ClipArgs &a, hipStream_t stream) {
 #define SS_CLIP_C5_SINGLE 1024, 24, 1, 4
 
 template <int ROWS, int BLOCK, int EPT, int FB, int WPE>
-void launch_shape(const ClipArgs &a, hipStream_t stream) {
+void launch_shape(const ClipArgs &a, int mode, hipStream_t stream) {
     static_assert(BLOCK * EPT >= ROWS, "a work-group holds the longest row of its class");
-    launch_regs<BLOCK, EPT, FB, WPE>(a, stream);
+    switch (mode) {
+        case MODE_FEATURES: launch_regs<BLOCK, EPT, FB, WPE, MODE_FEATURES>(a, stream); break;
+        case MODE_SURROGATE: launch_regs<BLOCK, EPT, FB, WPE, MODE_SURROGATE>(a, stream); break;
+        default: launch_regs<BLOCK, EPT, FB, WPE, MODE_CLIP>(a, stream); break;
+    }
 }
 
-void launch_class(const ClipArgs &a, int c, hipStream_t stream) {
+// (the streaming kernel serves the plain clip only; the surrogate entry
+// points refuse rows beyond class 5 before launching)
+void launch_class(const ClipArgs &a, int c, int mode, hipStream_t stream) {
     const bool batch = a.n_frames > 1;
     switch (c) {
-        case 0: batch ? launch_shape<1024, SS_CLIP_C0>(a, stream) : launch_shape<1024, SS_CLIP_C0_SINGLE>(a, stream); break;
-        case 1: batch ? launch_shape<2048, SS_CLIP_C1>(a, stream) : launch_shape<2048, SS_CLIP_C1_SINGLE>(a, stream); break;
-        case 2: batch ? launch_shape<4096, SS_CLIP_C2>(a, stream) : launch_shape<4096, SS_CLIP_C2_SINGLE>(a, stream); break;
-        case 3: batch ? launch_shape<8192, SS_CLIP_C3>(a, stream) : launch_shape<8192, SS_CLIP_C3_SINGLE>(a, stream); break;
-        case 4: batch ? launch_shape<16384, SS_CLIP_C4>(a, stream) : launch_shape<16384, SS_CLIP_C4_SINGLE>(a, stream); break;
-        case 5: batch ? launch_shape<24576, SS_CLIP_C5>(a, stream) : launch_shape<24576, SS_CLIP_C5_SINGLE>(a, stream); break;
+        case 0: batch ? launch_shape<1024, SS_CLIP_C0>(a, mode, stream) : launch_shape<1024, SS_CLIP_C0_SINGLE>(a, mode, stream); break;
+        case 1: batch ? launch_shape<2048, SS_CLIP_C1>(a, mode, stream) : launch_shape<2048, SS_CLIP_C1_SINGLE>(a, mode, stream); break;
+        case 2: batch ? launch_shape<4096, SS_CLIP_C2>(a, mode, stream) : launch_shape<4096, SS_CLIP_C2_SINGLE>(a, mode, stream); break;
+        case 3: batch ? launch_shape<8192, SS_CLIP_C3>(a, mode, stream) : launch_shape<8192, SS_CLIP_C3_SINGLE>(a, mode, stream); break;
+        case 4: batch ? launch_shape<16384, SS_CLIP_C4>(a, mode, stream) : launch_shape<16384, SS_CLIP_C4_SINGLE>(a, mode, stream); break;
+        case 5: batch ? launch_shape<24576, SS_CLIP_C5>(a, mode, stream) : launch_shape<24576, SS_CLIP_C5_SINGLE>(a, mode, stream); break;
         default: launch_stream<1024>(a, stream); break;
     }
 }
@@ -784,7 +1097,7 @@ int class_of(int32_t rows) {
 // kernels sized to the class); otherwise one launch sized to the longest
 // row.  The Poisson and hybrid models and an extra mask take the streaming
 // kernel.
-void dispatch(ClipArgs a, const ss_csr *csr, int n_frames, hipStream_t stream) {
+void dispatch(ClipArgs a, const ss_csr *csr, int n_frames, int mode, hipStream_t stream) {
     const bool regs = a.model == SS_AZIMUTHAL && a.mask == nullptr && a.n_pix < (int64_t(1) << 30);
     if (!regs) {
         a.bin_order = nullptr;
@@ -798,7 +1111,7 @@ void dispatch(ClipArgs a, const ss_csr *csr, int n_frames, hipStream_t stream) {
         a.bin_order = nullptr;
         a.order_base = 0;
         a.launch_bins = a.n_bins;
-        launch_class(a, class_of(csr->max_row), stream);
+        launch_class(a, class_of(csr->max_row), mode, stream);
         return;
     }
     int32_t base = 0;
@@ -808,7 +1121,7 @@ void dispatch(ClipArgs a, const ss_csr *csr, int n_frames, hipStream_t stream) {
         a.bin_order = csr->bin_order;
         a.order_base = base;
         a.launch_bins = cnt;
-        launch_class(a, c, stream);
+        launch_class(a, c, mode, stream);
         base += cnt;
     }
 }
@@ -816,10 +1129,22 @@ void dispatch(ClipArgs a, const ss_csr *csr, int n_frames, hipStream_t stream) {
 }  // namespace
 }  // namespace ss
 
-static int clip_entry(const float *frames, const float *norm, const uint8_t *mask, int32_t n_frames,
-                      const ss_csr *csr, const ss_params *p, const ss_profile *out, bool integrate_only,
-                      hipStream_t stream) {
-    if (!csr || !p || !out) return SS_EINVAL;
+namespace {
+
+struct SurrogateIo {
+    int mode = ss::MODE_CLIP;
+    float *features = nullptr;
+    double *stats0 = nullptr;
+    const uint16_t *w16 = nullptr;
+    int32_t max_verify = 0;
+    int32_t *accepted = nullptr;
+};
+
+int clip_entry(const float *frames, const float *norm, const uint8_t *mask, int32_t n_frames, const ss_csr *csr,
+               const ss_params *p, const ss_profile *out, bool integrate_only, const SurrogateIo &io,
+               hipStream_t stream) {
+    const bool features = io.mode == ss::MODE_FEATURES;
+    if (!csr || !p || (!features && !out)) return SS_EINVAL;
     if (n_frames < 0) return SS_ESIZE;
     if (csr->n_bins <= 0 || csr->n_bins > SS_MAX_BINS || csr->n_pix < 0 ||
         csr->n_pix >= (int64_t(1) << 31) || csr->nnz < 0 || csr->nnz >= (int64_t(1) << 31) ||
@@ -828,14 +1153,26 @@ static int clip_entry(const float *frames, const float *norm, const uint8_t *mas
     if (!integrate_only && (p->max_iter < 0 || p->max_iter > SS_MAX_ITER)) return SS_ESIZE;
     if (p->error_model != SS_AZIMUTHAL && p->error_model != SS_POISSON && p->error_model != SS_HYBRID)
         return SS_EINVAL;
+    if (io.mode != ss::MODE_CLIP) {
+        // the surrogate runs in the register kernel only
+        if (mask || csr->max_row > ss_class_rows(SS_N_CLASSES - 2) || csr->n_pix >= (int64_t(1) << 30))
+            return SS_EINVAL;
+        if (features && (!io.features || !io.stats0)) return SS_EINVAL;
+        if (io.mode == ss::MODE_SURROGATE &&
+            (p->error_model != SS_AZIMUTHAL || !(p->cutoff > 0.0f) || !io.w16 ||
+             (reinterpret_cast<uintptr_t>(io.w16) & 15u) != 0 || io.max_verify < 1 || io.max_verify > SS_MAX_ITER))
+            return SS_EINVAL;
+    }
     if (n_frames == 0) return SS_OK;
     if (csr->n_pix == 0 && csr->nnz > 0) return SS_ESIZE;
-    if (!frames || !csr->indptr || (csr->nnz > 0 && (!csr->indices || !csr->weight)) || !out->mean ||
-        !out->std || !out->sem || !out->sum_w || !out->n_members || !out->n_iter || !out->converged)
+    if (!frames || !csr->indptr || (csr->nnz > 0 && (!csr->indices || !csr->weight)))
+        return SS_EINVAL;
+    if (!features && (!out->mean || !out->std || !out->sem || !out->sum_w || !out->n_members || !out->n_iter ||
+                      !out->converged))
         return SS_EINVAL;
     const int64_t items = int64_t(csr->n_bins) * n_frames;
     if (items >= (int64_t(1) << 31) - 8) return SS_ESIZE;
-    ss::ClipArgs a;
+    ss::ClipArgs a{};
     a.frames = frames;
     a.n_pix = csr->n_pix;
     a.norm = norm;
@@ -853,13 +1190,20 @@ static int clip_entry(const float *frames, const float *norm, const uint8_t *mas
     a.max_iter = integrate_only ? 0 : p->max_iter;
     a.model = p->error_model;
     a.dark_var = double(p->dark_var);
-    a.mean = out->mean;
-    a.std = out->std;
-    a.sem = out->sem;
-    a.sum_w = out->sum_w;
-    a.n_members = out->n_members;
-    a.n_iter = out->n_iter;
-    a.converged = out->converged;
+    if (!features) {
+        a.mean = out->mean;
+        a.std = out->std;
+        a.sem = out->sem;
+        a.sum_w = out->sum_w;
+        a.n_members = out->n_members;
+        a.n_iter = out->n_iter;
+        a.converged = out->converged;
+    }
+    a.features = io.features;
+    a.stats0 = io.stats0;
+    a.w16 = io.w16;
+    a.max_verify = io.max_verify;
+    a.accepted = io.accepted;
     if (csr->bin_order) {
         int64_t sum = 0;
         for (int c = 0; c < SS_N_CLASSES; ++c) {
@@ -867,20 +1211,48 @@ static int clip_entry(const float *frames, const float *norm, const uint8_t *mas
             sum += csr->class_count[c];
         }
         if (sum != csr->n_bins) return SS_EINVAL;
+        if (io.mode != ss::MODE_CLIP && csr->class_count[SS_N_CLASSES - 1] != 0) return SS_EINVAL;
     }
-    ss::dispatch(a, csr, n_frames, stream);
+    ss::dispatch(a, csr, n_frames, io.mode, stream);
     SS_RETURN_IF_LAUNCH_FAILED();
     return SS_OK;
 }
 
+}  // namespace
+
 extern "C" int ss_sigma_clip(const float *frames, const float *norm, const uint8_t *mask,
                              int32_t n_frames, const ss_csr *csr, const ss_params *params,
                              const ss_profile *out, hipStream_t stream) {
-    return clip_entry(frames, norm, mask, n_frames, csr, params, out, false, stream);
+    return clip_entry(frames, norm, mask, n_frames, csr, params, out, false, SurrogateIo{}, stream);
 }
 
 extern "C" int ss_integrate(const float *frames, const float *norm, const uint8_t *mask,
                             int32_t n_frames, const ss_csr *csr, const ss_params *params,
                             const ss_profile *out, hipStream_t stream) {
-    return clip_entry(frames, norm, mask, n_frames, csr, params, out, true, stream);
+    return clip_entry(frames, norm, mask, n_frames, csr, params, out, true, SurrogateIo{}, stream);
+}
+
+extern "C" int ss_clip_features(const float *frames, const float *norm, const uint8_t *mask, int32_t n_frames,
+                                const ss_csr *csr, float *features, double *stats0, hipStream_t stream) {
+    ss_params p{};
+    p.cutoff = 3.0f;
+    p.max_iter = 0;
+    p.error_model = SS_AZIMUTHAL;
+    SurrogateIo io;
+    io.mode = ss::MODE_FEATURES;
+    io.features = features;
+    io.stats0 = stats0;
+    return clip_entry(frames, norm, mask, n_frames, csr, &p, nullptr, false, io, stream);
+}
+
+extern "C" int ss_sigma_clip_surrogate(const float *frames, const float *norm, const uint8_t *mask,
+                                       int32_t n_frames, const ss_csr *csr, const ss_params *params,
+                                       const uint16_t *w16, int32_t max_verify, const ss_profile *out,
+                                       int32_t *accepted, hipStream_t stream) {
+    SurrogateIo io;
+    io.mode = ss::MODE_SURROGATE;
+    io.w16 = w16;
+    io.max_verify = max_verify;
+    io.accepted = accepted;
+    return clip_entry(frames, norm, mask, n_frames, csr, params, out, false, io, stream);
 }

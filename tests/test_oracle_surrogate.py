@@ -141,23 +141,35 @@ def test_verified_clip_accepts_the_plain_fixed_point():
         omega = rng.uniform(0.5, 1.5, v.size)
         keep, m = _converged_plain(v, omega, 3.0)
         selfc = np.array_equal(np.abs(v - m["mean"]) <= 3.0 * m["std"], keep)
-        ok, E, mE = Q.verified_bin(v, omega, m["mean"], m["std"], 3.0, 1e-3)
+        ok, k, E, mE = Q.verified_bin(v, omega, m["mean"], m["std"], 3.0, 1)
         assert ok == selfc
         if ok:
             hits += 1
-            assert np.array_equal(E, keep)
+            assert k == 1 and np.array_equal(E, keep)
             assert mE["mean"] == m["mean"] and mE["std"] == m["std"]
+            # a prediction a little off reaches the same fixed point with one more pass
+            ok2, k2, E2, m2 = Q.verified_bin(v, omega, m["mean"] + 0.05 * m["std"], 1.03 * m["std"], 3.0, 3)
+            if ok2:
+                assert np.array_equal(E2, keep) and m2["mean"] == m["mean"]
     assert hits >= 20
 
 
-def test_verified_clip_rejects_a_poor_prediction():
+def test_verified_clip_accepts_only_fixed_points():
+    """A poor prediction is either rejected or, if its set happens to be the
+    fixed point, gives exactly the plain result; never anything else."""
     rng = np.random.default_rng(9)
     v = np.concatenate([rng.normal(10, 1, 500), rng.uniform(20, 60, 20)])
     omega = np.ones(v.size)
     keep, m = _converged_plain(v, omega, 3.0)
-    for mh, sh in ((m["mean"], 3 * m["std"]), (m["mean"] + m["std"], m["std"]), (m["mean"], 0.3 * m["std"])):
-        ok, _, _ = Q.verified_bin(v, omega, mh, sh, 3.0, 1e-3)
-        assert not ok
+    rejected = 0
+    for mh, sh in ((m["mean"], 3 * m["std"]), (m["mean"] + m["std"], m["std"]), (m["mean"], 0.3 * m["std"]),
+                   (m["mean"] - 2 * m["std"], 0.5 * m["std"])):
+        ok, k, E, mE = Q.verified_bin(v, omega, mh, sh, 3.0, 1)
+        if ok:
+            assert np.array_equal(E, keep) and mE["mean"] == m["mean"] and mE["std"] == m["std"]
+        else:
+            rejected += 1
+    assert rejected >= 2
 
 
 def test_surrogate_clip_falls_back_to_the_plain_clip():
@@ -168,7 +180,7 @@ def test_surrogate_clip_falls_back_to_the_plain_clip():
     frame = synth.float_frame(g, 0)[0]
     csr = G.csr_for(g, mask)
     p = Q.init_params(0)  # untrained: nearly every bin falls back
-    out = Q.surrogate_clip(frame, None, csr, p, mask, 3.0, 32)
+    out = Q.surrogate_clip(frame, None, csr, p, mask, 3.0, 32, 2)
     plain = S.sigma_clip(frame.reshape(-1), None, csr, mask.reshape(-1), 3.0, 32)
     rej = out["accepted"] == 0
     for k in ("mean", "std", "n_members", "n_iter", "converged"):
