@@ -377,21 +377,26 @@ int ss_mlp_grad(const uint16_t *w16, const float *x, const float *target, const 
 int ss_mlp_adam(float *params, float *m, float *v, const float *grad, int32_t step, float lr,
                 float beta1, float beta2, float eps, uint16_t *w16, hipStream_t stream);
 
-/* ss_sigma_clip_surrogate -- clipped profile with the surrogate: per (frame,
- * bin) the network predicts (mean, std); then up to max_verify verification
- * passes: E = members within cutoff x std of the mean, (mean, std) <- the
- * statistics of E, accepted when E is exactly the set of members within
- * cutoff x its own std of its own mean (a fixed point of the clip, so the
- * statistics carry no residual), |E| >= 2 and its std > 0.  An accepted bin's
- * profile holds E's statistics with n_iter = the verification passes used
- * and converged = 1.  Every other bin runs the plain clip of ss_sigma_clip
- * (params->max_iter passes).  Requires the azimuthal model, cutoff > 0,
- * mask NULL, rows within ss_class_rows(SS_N_CLASSES - 2), w16 16-byte
- * aligned and 1 <= max_verify <= SS_MAX_ITER.  accepted [dev] int32
- * [n_frames][n_bins] or NULL.  Errors: SS_EINVAL, SS_ESIZE, SS_EHIP. */
+/* ss_sigma_clip_surrogate -- the clip of ss_sigma_clip, warm-started by the
+ * surrogate.  Per (frame, bin) the network predicts the converged (mean,
+ * std); the first clipping pass removes the members outside the intersection
+ * of its own bounds (eq. clip on all members) and mean +- cutoff (1 + widen)
+ * std; the plain passes follow (params->max_iter in all).  A bin is accepted
+ * (state 1) when its clip converged with final bounds inside the predicted
+ * ones, so the first pass removed nothing the final bounds keep; a refused
+ * bin (state -1) is clipped again from scratch by a second, plain launch on
+ * the same stream; a bin without a usable prediction runs the plain clip
+ * (state 0): fewer than 64 members, zero spread, or a predicted interval
+ * mean - cutoff (1 + widen) std <= 0 (low counts), where the clip can have
+ * several fixed points and a warm start could settle on another one.  n_iter counts the passes that
+ * removed members, as in ss_sigma_clip.
+ * Requires the azimuthal model, cutoff > 0, widen >= 0, mask NULL, rows
+ * within ss_class_rows(SS_N_CLASSES - 2) and w16 16-byte aligned.
+ *   accepted [dev] int32 [n_frames][n_bins], required: the states above.
+ * Errors: SS_EINVAL, SS_ESIZE, SS_EHIP. */
 int ss_sigma_clip_surrogate(const float *frames, const float *norm, const uint8_t *mask,
                             int32_t n_frames, const ss_csr *csr, const ss_params *params,
-                            const uint16_t *w16, int32_t max_verify, const ss_profile *out,
+                            const uint16_t *w16, float widen, const ss_profile *out,
                             int32_t *accepted, hipStream_t stream);
 
 #ifdef __cplusplus

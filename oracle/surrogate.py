@@ -24,14 +24,19 @@ evaluates with every parameter rounded to float16 and float32-or-better
 arithmetic.  Loss: mean over the used samples of the squared error summed
 over the two outputs.
 
-Verified clip of one bin (cut-off c > 0), at most V verification passes:
-  (m0', s0') = (mean_hat, std_hat);  for k = 1 .. V:
-      E_k = {members with |v - m'_(k-1)| <= c s'_(k-1)};  (m'_k, s'_k) = stats of E_k;
-      accept when |E_k| >= 2, s'_k > 0 and E_k equals {members with
-      |v - m'_k| <= c s'_k} (the set reproduces itself: a fixed point of the
-      clip, so its statistics are exact, with no residual);
-  an accepted bin reports the statistics of E_k with n_iter = k and
-  converged = 1; any other bin falls back to the plain clip.
+Warm-started clip of one bin (cut-off c > 0, widening w >= 0):
+  pass 0 of the plain clip removes the members outside the intersection of
+  its own bounds (mean +- c std of all members) and the predicted bounds
+  mean_hat +- c (1 + w) std_hat; the passes after it are the plain clip's
+  (eq. clip, same stopping rule and pass limit).  The result is accepted
+  (state 1) when the clip converged, its final bounds lie inside the
+  predicted ones and the final set is exactly the members within the final
+  bounds (no removed member lies within them); otherwise (state -1) the bin
+  is clipped again from scratch by the plain clip.  A bin without a usable
+  prediction runs the plain clip (state 0): fewer than 64 members, zero
+  spread, or a predicted interval reaching zero (low counts); such bins can
+  have several fixed points (for low counts, one per photon-number cluster),
+  and a warm start could settle on another one.
 """
 
 from __future__ import annotations
@@ -46,6 +51,7 @@ N_IN, N_HID, N_OUT = 19, 64, 2
 K1 = 32            # input rows of W1 (19 used, the rest zero)
 OUT_PAD = 16       # columns of W3 / entries of b3 (2 used)
 THRESHOLDS = -3.75 + 0.5 * np.arange(16)
+MIN_MEMBERS = 64   # smallest bin the warm start is tried on
 
 # parameter layout (float offsets)
 OFF_W1 = 0
@@ -208,28 +214,36 @@ def adam(p, m, v, g, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
 
 # ---------------------------------------------------------------- verified clip
 
-def verified_bin(v, omega, mean_hat, std_hat, cutoff, max_verify):
-    """(accepted, passes, E mask, stats of E) for one bin and one prediction."""
+def warm_bin(v, omega, mean_hat, std_hat, cutoff, max_iter, widen):
+    """(state, keep, n_iter, converged) of the warm-started clip of one bin."""
     v = np.asarray(v, dtype=np.float64)
     omega = np.asarray(omega, dtype=np.float64)
-    mean, std = mean_hat, std_hat
-    E, m = None, None
-    for k in range(1, max_verify + 1):
-        E = np.abs(v - mean) <= cutoff * std
-        m = S.moments(v[E], omega[E])
-        if m["n"] < 2 or not (m["std"] > 0):
-            return False, k, E, m
-        again = np.abs(v - m["mean"]) <= cutoff * m["std"]
-        if np.array_equal(again, E):
-            return True, k, E, m
-        mean, std = m["mean"], m["std"]
-    return False, max_verify, E, m
+    keep = np.ones(v.size, dtype=bool)
+    n_iter, converged = 0, 0
+    half = cutoff * (1.0 + widen) * std_hat
+    for k in range(max_iter):
+        m = S.moments(v[keep], omega[keep])
+        dev = np.abs(v - m["mean"])
+        drop = keep & (dev > cutoff * m["std"])
+        if k == 0:
+            drop |= keep & (np.abs(v - mean_hat) > half)
+        if not drop.any():
+            converged = 1
+            break
+        keep &= ~drop
+        n_iter += 1
+    m = S.moments(v[keep], omega[keep])
+    inside = (m["mean"] - cutoff * m["std"] >= mean_hat - half) and (m["mean"] + cutoff * m["std"] <= mean_hat + half)
+    exact = np.array_equal(np.abs(v - m["mean"]) <= cutoff * m["std"], keep)
+    state = 1 if (converged and inside and exact) else -1
+    return state, keep, n_iter, converged
 
 
-def surrogate_clip(frame, norm, csr, p, mask=None, cutoff=3.0, max_iter=32, max_verify=2):
-    """Profile of one frame from the verified surrogate, plain clip as fallback.
+def surrogate_clip(frame, norm, csr, p, mask=None, cutoff=3.0, max_iter=32, widen=0.1):
+    """Profile of one frame from the warm-started clip, plain clip as fallback.
 
-    Returns the dict of ``stats.sigma_clip`` plus ``accepted`` per bin.
+    Returns the dict of ``stats.sigma_clip`` plus ``state`` per bin (1 warm
+    start accepted, 0 no prediction, -1 clipped again from scratch).
     """
     frame = np.asarray(frame).reshape(-1)
     normf = None if norm is None else np.asarray(norm).reshape(-1)
@@ -238,18 +252,22 @@ def surrogate_clip(frame, norm, csr, p, mask=None, cutoff=3.0, max_iter=32, max_
     X, st = features(frame, normf, csr, maskf)
     y = forward(p, X)
     out = {k: np.array(val, copy=True) for k, val in plain.items()}
-    out["accepted"] = np.zeros(csr.n_bins, dtype=np.int64)
+    out["state"] = np.zeros(csr.n_bins, dtype=np.int64)
     for r in range(csr.n_bins):
         n0, m0, s0 = st[r]
-        if n0 < 2 or not (s0 > 0):
+        if n0 < 2 or not (s0 > 0) or max_iter < 1:
             continue
         _, _, v, omega, _ = S.bin_members(frame, normf, csr, r, maskf)
         mean_hat = m0 + y[r, 0] * s0
         std_hat = s0 * math.exp(y[r, 1])
-        ok, k, E, m = verified_bin(v, omega, mean_hat, std_hat, cutoff, max_verify)
-        if not ok:
+        if n0 < MIN_MEMBERS or not (mean_hat - cutoff * (1.0 + widen) * std_hat > 0):
             continue
+        state, keep, n_iter, conv = warm_bin(v, omega, mean_hat, std_hat, cutoff, max_iter, widen)
+        out["state"][r] = state
+        if state != 1:
+            continue
+        m = S.moments(v[keep], omega[keep])
         out["mean"][r], out["std"][r], out["sem"][r] = m["mean"], m["std"], m["sem"]
         out["sum_w"][r], out["n_members"][r] = m["Omega"], m["n"]
-        out["n_iter"][r], out["converged"][r], out["accepted"][r] = k, 1, 1
+        out["n_iter"][r], out["converged"][r] = n_iter, conv
     return out

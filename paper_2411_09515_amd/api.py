@@ -281,18 +281,21 @@ class Surrogate:
         return hist
 
 
-def sigma_clip_surrogate(frames, geom: Geometry, params: Params, model: Surrogate, out=None, max_verify=2,
-                         accepted=None, norm=None):
-    """Clipped profile with the verified surrogate first, the plain clip elsewhere."""
-    _need_device(frames, norm, accepted)
+def sigma_clip_surrogate(frames, geom: Geometry, params: Params, model: Surrogate, out=None, widen=0.1,
+                         state=None, norm=None):
+    """The clip warm-started by the surrogate; ``state`` [F, nb] int32 receives
+    1 (accepted), 0 (no prediction) or -1 (refused, clipped again from scratch)."""
+    _need_device(frames, norm, state)
     F = frames.shape[0]
     if out is None:
         out = new_profile(F, geom.n_bins, frames.device)
+    if state is None:
+        state = torch.empty((F, geom.n_bins), dtype=torch.int32, device=frames.device)
     B.check("ss_sigma_clip_surrogate",
             B.lib().ss_sigma_clip_surrogate(_p(frames), _p(norm), None, F, ctypes.byref(geom.csr()),
-                                            ctypes.byref(params.c()), _p(model.w16), max_verify,
-                                            ctypes.byref(profile_c(out)), _p(accepted), _stream()))
-    return out
+                                            ctypes.byref(params.c()), _p(model.w16), widen,
+                                            ctypes.byref(profile_c(out)), _p(state), _stream()))
+    return out, state
 
 
 # -- classification ----------------------------------------------------------------------

@@ -132,7 +132,7 @@ def lib():
         L.ss_mlp_adam.restype = ctypes.c_int
         L.ss_mlp_adam.argtypes = [vp, vp, vp, vp, i32, f32, f32, f32, f32, vp, vp]
         L.ss_sigma_clip_surrogate.restype = ctypes.c_int
-        L.ss_sigma_clip_surrogate.argtypes = [vp, vp, vp, i32, P(Csr), P(Params), vp, i32, P(Profile), vp, vp]
+        L.ss_sigma_clip_surrogate.argtypes = [vp, vp, vp, i32, P(Csr), P(Params), vp, f32, P(Profile), vp, vp]
         _lib = L
     return _lib
 

@@ -62,8 +62,9 @@ struct ClipArgs {
     float *features;        // [F][nb][SS_MLP_IN], features mode
     double *stats0;         // [F][nb][3], features mode
     const uint16_t *w16;    // [SS_MLP_PARAMS] float16 bits, surrogate mode
-    int32_t max_verify;     // verification passes, surrogate mode
-    int32_t *accepted;      // [F][nb] or null, surrogate mode
+    double widen;           // widening of the predicted bounds, surrogate mode
+    int32_t *accepted;      // [F][nb] states, surrogate mode (1 accepted, 0 none, -1 refused)
+    const int32_t *redo;    // plain launch after the surrogate: process groups with state -1 only
 };
 
 // What k_clip_regs computes: the clipped profile, the surrogate's features
@@ -302,16 +303,18 @@ __device__ inline void add_removed(double (&r)[NREM], double w, double d) {
 // wave f % NW sums the lists of frame f in a fixed order (deterministic),
 // takes the sums off the running state and plans the frame's next pass.  A wave
 // whose list fills up stops and asks for another round of the same pass.
+// Smallest bin the warm start is tried on.
+constexpr int kWarmMinMembers = 64;
+
 // Per-frame surrogate state, in LDS.
 struct Surrogate {
     double n0, m0, s0;          // unclipped statistics
     double mean_hat, std_hat;   // the network's prediction
-    double mean, std, sem, sum_w, n;  // statistics of E
-    float lo, hi;               // E = members with lo <= v <= hi
-    ClipBounds again;           // clip bounds of E's own statistics
+    double half;                // predicted keep half-width cutoff (1 + widen) std_hat
+    ClipBounds fin;             // bounds of the final statistics
     int on;                     // a real frame with members
-    int verify;                 // a prediction to verify
-    int accepted;
+    int warm;                   // pass 0 uses the prediction
+    int back;                   // a removed member lies within the final bounds
 };
 
 __device__ inline float half_to_float(uint16_t h) { return __half2float(__ushort_as_half(h)); }
@@ -328,16 +331,13 @@ __device__ inline void wave_sync() {
 
 // The surrogate stage of k_clip_regs, after the first evaluation: the
 // 16-point sketch and the features; in surrogate mode also the network's
-// prediction (wave 0, one hidden unit per lane) and up to max_verify
-// verification passes (the statistics of the member set E the current
-// estimate selects, and the check that E reproduces itself).  Accepted frames
-// get their profile written here and take no clipping pass.
+// prediction (wave 0, one hidden unit per lane), which narrows the bounds of
+// the first clipping pass (a warm start of the plain passes that follow).
 // Returns true when the work-group is done (features mode).
 template <int BLOCK, int EPT, int FB, int MODE>
-__device__ inline bool surrogate_stage(const ClipArgs &a, float2v (&vp)[FB][EPT / 2], const float *w_s,
-                                       uint32_t *hist, float (*sk_s)[16], float (*feat_s)[SS_MLP_IN],
-                                       Surrogate *sur_s, const uint16_t *wts_s, float *h1_s, int *bad_s,
-                                       double *wstat, PassCtl *ctl, int f0, int nf, int bin) {
+__device__ inline bool surrogate_stage(const ClipArgs &a, float2v (&vp)[FB][EPT / 2], uint32_t *hist,
+                                       float (*sk_s)[16], float (*feat_s)[SS_MLP_IN], Surrogate *sur_s,
+                                       const uint16_t *wts_s, float *h1_s, PassCtl *ctl, int f0, int nf, int bin) {
     constexpr int NW = BLOCK / kWave;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
 
@@ -428,134 +428,28 @@ __device__ inline bool surrogate_stage(const ClipArgs &a, float2v (&vp)[FB][EPT 
             const double y1 = wave_sum(double(h2 * w31)) + double(b31);
             if (lane == 0) {
                 Surrogate u = sur_s[f];
-                u.verify = u.on && u.n0 >= 2.0 && u.s0 > 0.0;
                 u.mean_hat = u.m0 + y0 * u.s0;
                 u.std_hat = u.s0 * exp(y1);
-                const double thr = a.cutoff * u.std_hat;
-                // |v - mean_hat| <= thr exactly when lo <= v <= hi
-                u.lo = __double2float_ru(u.mean_hat - thr);
-                u.hi = __double2float_rd(u.mean_hat + thr);
-                u.accepted = 0;
+                u.half = a.cutoff * (1.0 + a.widen) * u.std_hat;
+                // no warm start in small bins or where the predicted interval reaches
+                // zero (low counts): their clip can have several fixed points (for low
+                // counts one per photon-number cluster), and a warm start could settle
+                // on another one than the plain clip
+                u.warm = u.on && u.n0 >= double(kWarmMinMembers) && u.s0 > 0.0 && ctl[f].go &&
+                         u.mean_hat - u.half > 0.0;
+                if (u.warm) {
+                    // pass 0 keeps the members within both its own bounds and
+                    // |v - mean_hat| <= half, i.e. RU32(mean_hat - half) <= v <= RD32(mean_hat + half)
+                    PassCtl c = ctl[f];
+                    c.bounds.lo = fmaxf(c.bounds.lo, __double2float_ru(u.mean_hat - u.half));
+                    c.bounds.hi = fminf(c.bounds.hi, __double2float_rd(u.mean_hat + u.half));
+                    ctl[f] = c;
+                }
                 sur_s[f] = u;
             }
         }
     }
     __syncthreads();
-
-    // verification passes: E from the current (mean, std), E's statistics
-    // (shifted by that mean), then whether E reproduces itself
-    for (int k = 1; k <= a.max_verify; ++k) {
-        {
-            double t[FB][6];
-#pragma unroll
-            for (int f = 0; f < FB; ++f) {
-#pragma unroll
-                for (int q = 0; q < 6; ++q) t[f][q] = 0.0;
-                if (!sur_s[f].verify) continue;
-                const float lo = sur_s[f].lo, hi = sur_s[f].hi;
-                const double Kf = sur_s[f].mean_hat;
-#pragma unroll
-                for (int e = 0; e < EPT; ++e) {
-                    const float x = SS_V(f, e);
-                    const float w = w_s[e * BLOCK + tid];
-                    const bool in = x >= lo && x <= hi;
-                    const double wz = double(in ? w : 0.0f);
-                    const double d = double(in ? x : 0.0f) - Kf;
-                    const double wd = wz * d;
-                    t[f][0] += wz;
-                    t[f][1] += wd;
-                    t[f][2] = fma(wz, wz, t[f][2]);
-                    t[f][3] = fma(wz, wd, t[f][3]);
-                    t[f][4] = fma(wd, wd, t[f][4]);
-                    t[f][5] += in ? 1.0 : 0.0;
-                }
-#pragma unroll
-                for (int q = 0; q < 6; ++q) t[f][q] = wave_sum_last(t[f][q]);
-                if (lane == kWave - 1) {
-#pragma unroll
-                    for (int q = 0; q < 6; ++q) wstat[(f * NW + wid) * NWSTAT + q] = t[f][q];
-                }
-            }
-        }
-        __syncthreads();
-        if (tid < FB && sur_s[tid].verify) {
-            const int f = tid;
-            Surrogate u = sur_s[f];
-            double sm[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-#pragma unroll 1
-            for (int w = 0; w < NW; ++w)
-#pragma unroll
-                for (int q = 0; q < 6; ++q) sm[q] += wstat[(f * NW + w) * NWSTAT + q];
-            if (sm[5] >= 1.5 && sm[0] > 0.0) {
-                const double delta = sm[1] / sm[0];
-                double vv = sm[4] - 2.0 * delta * sm[3] + delta * delta * sm[2];
-                vv = vv > 0.0 ? vv : 0.0;
-                u.mean = u.mean_hat + delta;
-                u.std = sqrt(vv / sm[2]);
-                u.sem = sqrt(vv) / sm[0];
-                u.sum_w = sm[0];
-                u.n = sm[5];
-                u.again = clip_bounds(u.mean, a.cutoff * u.std);
-                u.verify = u.std > 0.0;
-            } else {
-                u.verify = 0;
-            }
-            sur_s[f] = u;
-        }
-        __syncthreads();
-        // E must be exactly the members within the clip bounds of E's statistics
-#pragma unroll
-        for (int f = 0; f < FB; ++f) {
-            if (!sur_s[f].verify) continue;
-            const float lo = sur_s[f].lo, hi = sur_s[f].hi;
-            const ClipBounds again = sur_s[f].again;
-            bool bad = false;
-#pragma unroll
-            for (int e = 0; e < EPT; ++e) {
-                const float x = SS_V(f, e);
-                const bool in_e = x >= lo && x <= hi;
-                const bool in_again = (x == x) && !clipped(x, again);
-                bad = bad || (in_e != in_again);
-            }
-            const uint64_t m = __ballot(bad);
-            if (lane == 0) bad_s[f * NW + wid] = m != 0;
-        }
-        __syncthreads();
-        if (tid < FB && sur_s[tid].verify) {
-            const int f = tid;
-            Surrogate u = sur_s[f];
-            bool bad = false;
-            for (int w = 0; w < NW; ++w) bad = bad || bad_s[f * NW + w];
-            if (!bad) {
-                u.accepted = 1;
-                u.verify = 0;
-                if (f < nf) {
-                    const int64_t o = int64_t(f0 + f) * a.n_bins + bin;
-                    a.mean[o] = u.mean;
-                    a.std[o] = u.std;
-                    a.sem[o] = u.sem;
-                    a.sum_w[o] = u.sum_w;
-                    a.n_members[o] = int32_t(u.n);
-                    a.n_iter[o] = k;
-                    a.converged[o] = 1;
-                }
-                ctl[f].go = 0;
-            } else {
-                // the next E: the members within E's own bounds
-                u.lo = u.again.lo;
-                u.hi = u.again.hi;
-                u.mean_hat = u.mean;
-                u.verify = k < a.max_verify;
-            }
-            sur_s[f] = u;
-        }
-        __syncthreads();
-        bool any = false;
-#pragma unroll
-        for (int f = 0; f < FB; ++f) any = any || sur_s[f].verify;
-        if (!any) break;
-    }
-    if (tid < nf && a.accepted) a.accepted[int64_t(f0 + tid) * a.n_bins + bin] = sur_s[tid].accepted;
     return false;
 }
 
@@ -572,7 +466,6 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) vo
     __shared__ Surrogate sur_s[FB];
     __shared__ uint16_t wts_s[SUR ? SS_MLP_PARAMS : 2];
     __shared__ float h1_s[SUR ? FB : 1][SS_MLP_HID];
-    __shared__ int bad_s[SUR ? FB : 1][SUR ? NW : 1];
     __shared__ float w_s[EPT * BLOCK];
     __shared__ float2 rem_s[NW][FB][kRemCap];
     __shared__ int cnt_s[NW][FB];
@@ -590,6 +483,12 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) vo
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const int wid = tid / kWave;
+    if (a.redo) {
+        // a second, plain launch after the surrogate: only groups holding a refused frame
+        bool any = false;
+        for (int f = 0; f < nf; ++f) any = any || a.redo[int64_t(f0 + f) * a.n_bins + bin] == -1;
+        if (!any) return;
+    }
     int64_t start, end;
     row_bounds(a, bin, start, end);
     const int len = int(end - start);
@@ -600,10 +499,10 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) vo
             if constexpr (MODE == MODE_FEATURES) {
                 for (int q = 0; q < SS_MLP_IN; ++q) a.features[o * SS_MLP_IN + q] = 0.0f;
                 for (int q = 0; q < 3; ++q) a.stats0[o * 3 + q] = 0.0;
-            } else {
+            } else if (a.redo == nullptr || a.redo[o] == -1) {
                 const double z[NSUM] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
                 write_profile(a, f0 + tid, bin, z, Stats{0.0, 0.0, 0.0, 0.0, 0.0}, 0, a.max_iter > 0 ? 1 : 0);
-                if (SUR && a.accepted) a.accepted[o] = 0;
+                if (SUR) a.accepted[o] = 0;
             }
         }
         return;
@@ -793,10 +692,17 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) vo
     }
     __syncthreads();
     if constexpr (SKETCH) {
-        if (surrogate_stage<BLOCK, EPT, FB, MODE>(a, vp, w_s, &hist[0][0][0], sk_s, feat_s, sur_s, wts_s, &h1_s[0][0],
-                                                  &bad_s[0][0], &wstat[0][0][0], ctl, f0, nf, bin))
+        if (surrogate_stage<BLOCK, EPT, FB, MODE>(a, vp, &hist[0][0][0], sk_s, feat_s, sur_s, wts_s, &h1_s[0][0], ctl, f0,
+                                                  nf, bin))
             return;
     }
+
+    // members removed by a pass (surrogate mode keeps their values; the
+    // other modes overwrite a removed value with NaN instead)
+    uint64_t gone[FB];
+#pragma unroll
+    for (int f = 0; f < FB; ++f) gone[f] = 0;
+    static_assert(!SUR || EPT <= 64, "removal flags live in one 64-bit word");
 
     // rejection passes
     for (int k = 0;; ++k) {
@@ -812,7 +718,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) vo
             double t[NSUM] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
             for (int e = 0; e < EPT; ++e)
-                if (SS_V(f, e) == SS_V(f, e)) add_member(t, double(w_s[e * BLOCK + tid]), double(SS_V(f, e)) - Kn, 0.0);
+                if (SS_V(f, e) == SS_V(f, e) && !(SUR && ((gone[f] >> e) & 1u)))
+                    add_member(t, double(w_s[e * BLOCK + tid]), double(SS_V(f, e)) - Kn, 0.0);
             block_sum<NSUM, BLOCK>(t, part, tot);
             if (tid == 0) {
                 t[S_N] = rint(t[S_N]);
@@ -844,7 +751,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) vo
                     const ClipBounds bnd = ctl[f].bounds;
 #pragma unroll
                     for (int e = 0; e < EPT; ++e) {
-                        const bool out = clipped(SS_V(f, e), bnd);
+                        const bool out = !(SUR && ((gone[f] >> e) & 1u)) && clipped(SS_V(f, e), bnd);
                         const uint64_t m = __ballot(out);
                         if (m == 0) continue;
                         const int cnt = __popcll(m);
@@ -854,7 +761,10 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) vo
                         }
                         if (out) {
                             rem_s[wid][f][used + lanes_below(m)] = make_float2(w_s[e * BLOCK + tid], SS_V(f, e));
-                            SS_V(f, e) = __builtin_nanf("");
+                            if constexpr (SUR)
+                                gone[f] |= uint64_t(1) << e;  // the value stays for the final check
+                            else
+                                SS_V(f, e) = __builtin_nanf("");
                         }
                         used = __builtin_amdgcn_readfirstlane(used + cnt);
                     }
@@ -903,10 +813,49 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) vo
             if (!again) break;
         }
     }
-    if (tid < nf && !(SUR && sur_s[tid].accepted)) {
-        double sv[NSUM];
-        load_state(state[tid], sv);
-        write_profile(a, f0 + tid, bin, sv, stats_from(sv, ctl[tid].K), ctl[tid].n_iter, ctl[tid].converged);
+    if constexpr (SUR) {
+        // a warm start is accepted only if no removed member lies within the
+        // final bounds (the final set is exactly the members the final bounds keep)
+        if (tid < FB) {
+            double sv[NSUM];
+            load_state(state[tid], sv);
+            const Stats st = stats_from(sv, ctl[tid].K);
+            sur_s[tid].fin = clip_bounds(st.mean, a.cutoff * st.std);
+            sur_s[tid].back = 0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int f = 0; f < FB; ++f) {
+            if (!sur_s[f].warm) continue;
+            const ClipBounds fin = sur_s[f].fin;
+            bool back = false;
+#pragma unroll
+            for (int e = 0; e < EPT; ++e)
+                back = back || (((gone[f] >> e) & 1u) && !clipped(SS_V(f, e), fin));
+            if (__ballot(back) != 0 && lane == 0) atomicOr(&sur_s[f].back, 1);
+        }
+        __syncthreads();
+    }
+    if (tid < nf) {
+        const int64_t o = int64_t(f0 + tid) * a.n_bins + bin;
+        if (a.redo == nullptr || a.redo[o] == -1) {
+            double sv[NSUM];
+            load_state(state[tid], sv);
+            const Stats st = stats_from(sv, ctl[tid].K);
+            write_profile(a, f0 + tid, bin, sv, st, ctl[tid].n_iter, ctl[tid].converged);
+            if constexpr (SUR) {
+                // accepted when the clip converged inside the predicted bounds, so pass 0
+                // removed nothing the final bounds keep; else clipped again from scratch
+                const Surrogate u = sur_s[tid];
+                int state_out = 0;
+                if (u.warm) {
+                    const bool inside = st.mean - a.cutoff * st.std >= u.mean_hat - u.half &&
+                                        st.mean + a.cutoff * st.std <= u.mean_hat + u.half;
+                    state_out = (ctl[tid].converged && inside && !u.back) ? 1 : -1;
+                }
+                a.accepted[o] = state_out;
+            }
+        }
     }
 }
 #undef SS_V
@@ -1136,7 +1085,7 @@ struct SurrogateIo {
     float *features = nullptr;
     double *stats0 = nullptr;
     const uint16_t *w16 = nullptr;
-    int32_t max_verify = 0;
+    float widen = 0.0f;
     int32_t *accepted = nullptr;
 };
 
@@ -1160,7 +1109,7 @@ int clip_entry(const float *frames, const float *norm, const uint8_t *mask, int3
         if (features && (!io.features || !io.stats0)) return SS_EINVAL;
         if (io.mode == ss::MODE_SURROGATE &&
             (p->error_model != SS_AZIMUTHAL || !(p->cutoff > 0.0f) || !io.w16 ||
-             (reinterpret_cast<uintptr_t>(io.w16) & 15u) != 0 || io.max_verify < 1 || io.max_verify > SS_MAX_ITER))
+             (reinterpret_cast<uintptr_t>(io.w16) & 15u) != 0 || !(io.widen >= 0.0f) || !io.accepted))
             return SS_EINVAL;
     }
     if (n_frames == 0) return SS_OK;
@@ -1202,7 +1151,7 @@ int clip_entry(const float *frames, const float *norm, const uint8_t *mask, int3
     a.features = io.features;
     a.stats0 = io.stats0;
     a.w16 = io.w16;
-    a.max_verify = io.max_verify;
+    a.widen = double(io.widen);
     a.accepted = io.accepted;
     if (csr->bin_order) {
         int64_t sum = 0;
@@ -1214,6 +1163,11 @@ int clip_entry(const float *frames, const float *norm, const uint8_t *mask, int3
         if (io.mode != ss::MODE_CLIP && csr->class_count[SS_N_CLASSES - 1] != 0) return SS_EINVAL;
     }
     ss::dispatch(a, csr, n_frames, io.mode, stream);
+    if (io.mode == ss::MODE_SURROGATE) {
+        // the groups holding a refused bin, clipped again from scratch
+        a.redo = io.accepted;
+        ss::dispatch(a, csr, n_frames, ss::MODE_CLIP, stream);
+    }
     SS_RETURN_IF_LAUNCH_FAILED();
     return SS_OK;
 }
@@ -1247,12 +1201,12 @@ extern "C" int ss_clip_features(const float *frames, const float *norm, const ui
 
 extern "C" int ss_sigma_clip_surrogate(const float *frames, const float *norm, const uint8_t *mask,
                                        int32_t n_frames, const ss_csr *csr, const ss_params *params,
-                                       const uint16_t *w16, int32_t max_verify, const ss_profile *out,
+                                       const uint16_t *w16, float widen, const ss_profile *out,
                                        int32_t *accepted, hipStream_t stream) {
     SurrogateIo io;
     io.mode = ss::MODE_SURROGATE;
     io.w16 = w16;
-    io.max_verify = max_verify;
+    io.widen = widen;
     io.accepted = accepted;
     return clip_entry(frames, norm, mask, n_frames, csr, params, out, false, io, stream);
 }

@@ -8,7 +8,8 @@ computes none of the method's steps: no binning, no CSR, no correction of raw
 words, no statistics, no clipping, no classification.
 
 Every draw comes from ``numpy.random.default_rng`` seeded with a
-``SeedSequence([config_id, frame_idx])`` (calibration: ``[config_id, 999999]``),
+``SeedSequence([config_id, frame_idx])`` (calibration: ``[config_id, 999999]``;
+the clip surrogate's training frames: ``[config_id, 1000000 + frame_idx]``),
 so both sides see identical bytes.
 """
 
@@ -30,4 +31,5 @@ from .scene import (  # noqa: F401
     jungfrau_frame,
     float_frames,
     jungfrau_frames,
+    training_frame,
 )

@@ -240,8 +240,28 @@ def jungfrau_frame(geom: Geometry, frame_idx: int):
 
     Truth: dict(photons=float64 [H, W], level=int8 [H, W], spots=[n, 3]).
     """
-    ped, gain = jungfrau_calibration(geom)
     rng, photons, truth = _photons(geom, frame_idx)
+    return _encode(geom, rng, photons, truth)
+
+
+def training_frame(geom: Geometry, frame_idx: int):
+    """One raw frame of the clip surrogate's training set, from a seed stream
+    of its own (disjoint from ``jungfrau_frame``'s): the background ring
+    scaled by U[0.5, 4]; a hit with probability h ~ U[0, 0.5], a hit holding
+    1-500 spots (the spot model of the other frames)."""
+    rng = np.random.default_rng(np.random.SeedSequence([geom.config_id, 1_000_000 + frame_idx]))
+    ring = rng.uniform(0.5, 4.0)
+    hit = rng.random() < rng.uniform(0.0, 0.5)
+    n_spots = int(rng.integers(1, 501)) if hit else 0
+    spots, truth = spot_expectation(rng, geom, stripe_mask(geom), n_spots)
+    photons = rng.poisson(ring * _expected_background(geom) + spots).astype(np.float64)
+    word, info = _encode(geom, rng, photons, truth)
+    info.update(ring=ring, hit=hit)
+    return word, info
+
+
+def _encode(geom: Geometry, rng: np.random.Generator, photons: np.ndarray, truth):
+    ped, gain = jungfrau_calibration(geom)
     e = photons.reshape(-1)
     u = rng.random(e.size)
     level = np.where(u < GAIN_LEVEL_PROB[0], 0,

@@ -130,59 +130,53 @@ def test_targets_round_trip():
 def _converged_plain(v, omega, cutoff):
     keep, n_iter, conv, _ = S._clip_bin(v, omega, np.zeros_like(v), cutoff, 64, S.AZIMUTHAL)
     assert conv == 1
-    return keep, S.moments(v[keep], omega[keep])
+    return keep, S.moments(v[keep], omega[keep]), n_iter
 
 
-def test_verified_clip_accepts_the_plain_fixed_point():
+def test_warm_start_from_the_converged_answer_reproduces_the_plain_clip():
+    """A prediction equal to the plain clip's converged statistics reaches
+    the same member set in fewer passes, and is accepted."""
     rng = np.random.default_rng(8)
-    hits = 0
+    saved = 0
     for trial in range(30):
         v = np.concatenate([rng.normal(10, 1, 400), rng.uniform(15, 60, rng.integers(0, 30))])
         omega = rng.uniform(0.5, 1.5, v.size)
-        keep, m = _converged_plain(v, omega, 3.0)
-        selfc = np.array_equal(np.abs(v - m["mean"]) <= 3.0 * m["std"], keep)
-        ok, k, E, mE = Q.verified_bin(v, omega, m["mean"], m["std"], 3.0, 1)
-        assert ok == selfc
-        if ok:
-            hits += 1
-            assert k == 1 and np.array_equal(E, keep)
-            assert mE["mean"] == m["mean"] and mE["std"] == m["std"]
-            # a prediction a little off reaches the same fixed point with one more pass
-            ok2, k2, E2, m2 = Q.verified_bin(v, omega, m["mean"] + 0.05 * m["std"], 1.03 * m["std"], 3.0, 3)
-            if ok2:
-                assert np.array_equal(E2, keep) and m2["mean"] == m["mean"]
-    assert hits >= 20
+        keep, m, n_plain = _converged_plain(v, omega, 3.0)
+        state, kw, n_warm, conv = Q.warm_bin(v, omega, m["mean"], m["std"], 3.0, 64, 0.1)
+        assert conv == 1 and np.array_equal(kw, keep)
+        assert state == 1
+        assert n_warm <= n_plain
+        saved += n_plain - n_warm
+    assert saved > 0
 
 
-def test_verified_clip_accepts_only_fixed_points():
-    """A poor prediction is either rejected or, if its set happens to be the
-    fixed point, gives exactly the plain result; never anything else."""
-    rng = np.random.default_rng(9)
-    v = np.concatenate([rng.normal(10, 1, 500), rng.uniform(20, 60, 20)])
+def test_warm_start_with_zero_widening_is_at_least_as_tight():
+    rng = np.random.default_rng(10)
+    v = np.concatenate([rng.normal(0, 1, 2000), rng.uniform(5, 30, 50)])
     omega = np.ones(v.size)
-    keep, m = _converged_plain(v, omega, 3.0)
-    rejected = 0
-    for mh, sh in ((m["mean"], 3 * m["std"]), (m["mean"] + m["std"], m["std"]), (m["mean"], 0.3 * m["std"]),
-                   (m["mean"] - 2 * m["std"], 0.5 * m["std"])):
-        ok, k, E, mE = Q.verified_bin(v, omega, mh, sh, 3.0, 1)
-        if ok:
-            assert np.array_equal(E, keep) and mE["mean"] == m["mean"] and mE["std"] == m["std"]
-        else:
-            rejected += 1
-    assert rejected >= 2
+    keep, m, _ = _converged_plain(v, omega, 3.0)
+    # a prediction a little too tight removes members the plain clip keeps: refused
+    state, kw, _, _ = Q.warm_bin(v, omega, m["mean"], 0.8 * m["std"], 3.0, 64, 0.0)
+    assert state == -1
+    # a looser prediction removes only what the plain clip removes too
+    state, kw, _, _ = Q.warm_bin(v, omega, m["mean"], 1.5 * m["std"], 3.0, 64, 0.0)
+    assert state == 1 and np.array_equal(kw, keep)
 
 
-def test_surrogate_clip_falls_back_to_the_plain_clip():
+def test_surrogate_clip_equals_the_plain_clip_where_refused():
     from oracle import geometry as G
     import synth
     g = synth.SMALL
     mask = synth.stripe_mask(g)
     frame = synth.float_frame(g, 0)[0]
     csr = G.csr_for(g, mask)
-    p = Q.init_params(0)  # untrained: nearly every bin falls back
-    out = Q.surrogate_clip(frame, None, csr, p, mask, 3.0, 32, 2)
+    p = Q.init_params(0)  # untrained
+    out = Q.surrogate_clip(frame, None, csr, p, mask, 3.0, 32, 0.1)
     plain = S.sigma_clip(frame.reshape(-1), None, csr, mask.reshape(-1), 3.0, 32)
-    rej = out["accepted"] == 0
+    rej = out["state"] != 1
     for k in ("mean", "std", "n_members", "n_iter", "converged"):
         assert np.array_equal(out[k][rej], plain[k][rej])
-    assert rej.sum() > 0
+    # accepted bins hold the plain clip's member set too
+    acc = ~rej
+    assert np.array_equal(out["n_members"][acc], plain["n_members"][acc])
+    assert np.allclose(out["mean"][acc], plain["mean"][acc], rtol=1e-12)
