@@ -58,7 +58,8 @@ extern "C" {
 #define SS_MAX_BINS 4094
 #define SS_MAX_ITER 32
 #define SS_MAX_PATCH 15
-#define SS_N_CLASSES 7
+#define SS_N_CLASSES 8
+#define SS_SURROGATE_MAX_CLASS 5 /* the surrogate serves row-length classes 0..5 */
 
 /*
  * Pixel-to-bin matrix in CSR form (rows = radial bins), Sec. 2.2: the
@@ -71,6 +72,9 @@ extern "C" {
  * by row-length class, longest class first, and class_count[c] is the number
  * of bins in class c; the clip then launches one work-group size per class.
  * With bin_order == NULL one work-group size fits the longest row.
+ * shape[c] selects the work-group shape the clip uses for class c in
+ * batches of more than one frame: 0 (the default) or one of the
+ * alternatives 1, 2 (an autotuner's choice); any other value means 0.
  */
 typedef struct {
     int32_t n_bins;
@@ -82,6 +86,7 @@ typedef struct {
     const float *weight;      /* [dev] [nnz]          */
     const int32_t *bin_order; /* [dev] [n_bins] or NULL */
     int32_t class_count[SS_N_CLASSES];
+    int32_t shape[SS_N_CLASSES];
 } ss_csr;
 
 /*
@@ -233,6 +238,26 @@ int ss_integrate(const float *frames, const float *norm, const uint8_t *mask,
                  int32_t n_frames, const ss_csr *csr, const ss_params *params,
                  const ss_profile *out, hipStream_t stream);
 
+/* One batch of frames with its own geometry, for ss_sigma_clip_batches. */
+typedef struct {
+    const float *frames;    /* [dev] [n_frames][csr->n_pix] corrected intensity */
+    const float *norm;      /* [dev] [csr->n_pix] or NULL (Poisson / hybrid models) */
+    int32_t n_frames;
+    const ss_csr *csr;      /* [host] struct of [dev] arrays */
+    const ss_profile *out;  /* [host] struct of [dev] [n_frames][csr->n_bins] arrays */
+} ss_clip_batch;
+
+/* ss_sigma_clip_batches -- ss_sigma_clip of several batches, each with its
+ * own geometry (uneven detectors and bin counts), in one launch per
+ * row-length class for all of them: same results as one ss_sigma_clip call
+ * per batch.  Every batch needs a scheduled CSR, the azimuthal model and more
+ * than one frame for the shared launches (otherwise it is clipped on its own
+ * within this call); the work-group shape of each class is taken from
+ * batches[0].csr->shape.  Errors: SS_EINVAL, SS_ESIZE, SS_EHIP (checked for
+ * every batch before anything is launched). */
+int ss_sigma_clip_batches(const ss_clip_batch *batches, int32_t n_batches,
+                          const ss_params *params, hipStream_t stream);
+
 /*
  * ss_sigma_clip -- per-bin iterative sigma-clipping (eq. clip, Sec. 2.4).
  * For every frame and bin: members = CSR entries whose pixel is unmasked
@@ -339,7 +364,7 @@ int ss_peakfind(const float *frames, const uint8_t *mask, int32_t n_frames,
 
 /* ss_clip_features -- the surrogate's inputs for every (frame, bin).
  *   frames, norm: as ss_sigma_clip; mask must be NULL (masks are folded into
- *     the CSR) and rows must not exceed ss_class_rows(SS_N_CLASSES - 2).
+ *     the CSR) and rows must not exceed ss_class_rows(SS_SURROGATE_MAX_CLASS).
  *   features [dev] float [n_frames][n_bins][SS_MLP_IN] (all 0 for an empty bin)
  *   stats0 [dev] double [n_frames][n_bins][3]: n, m0, s0 (unclipped).
  * Errors: SS_EINVAL (null pointers, a mask, a row too long), SS_ESIZE, SS_EHIP. */
@@ -391,7 +416,7 @@ int ss_mlp_adam(float *params, float *m, float *v, const float *grad, int32_t st
  * several fixed points and a warm start could settle on another one.  n_iter counts the passes that
  * removed members, as in ss_sigma_clip.
  * Requires the azimuthal model, cutoff > 0, widen >= 0, mask NULL, rows
- * within ss_class_rows(SS_N_CLASSES - 2) and w16 16-byte aligned.
+ * within ss_class_rows(SS_SURROGATE_MAX_CLASS) and w16 16-byte aligned.
  *   accepted [dev] int32 [n_frames][n_bins], required: the states above.
  * Errors: SS_EINVAL, SS_ESIZE, SS_EHIP. */
 int ss_sigma_clip_surrogate(const float *frames, const float *norm, const uint8_t *mask,

@@ -105,6 +105,7 @@ class Geometry:
         self.rcoord = torch.from_numpy(h["rcoord"].view(np.int32)).to(dev)
         self.bin_order = torch.from_numpy(h["bin_order"]).to(dev)
         self.class_count = h["class_count"]
+        self.shape = [0] * B.SS_N_CLASSES   # work-group shape variant per class (see autotune)
         self.scheduled = True
         self.norm = None if norm is None else torch.from_numpy(
             np.array(norm, dtype=np.float32).reshape(-1)).to(dev)
@@ -121,9 +122,10 @@ class Geometry:
     def csr(self) -> B.Csr:
         """The C struct; with ``scheduled`` the clip launches per row-length class."""
         counts = (ctypes.c_int32 * B.SS_N_CLASSES)(*[int(c) for c in self.class_count])
+        shape = (ctypes.c_int32 * B.SS_N_CLASSES)(*[int(c) for c in self.shape])
         return B.Csr(self.n_bins, self.max_row, self.n_pix, self.nnz, self.indptr.data_ptr(),
                      self.indices.data_ptr(), self.weight.data_ptr(),
-                     self.bin_order.data_ptr() if self.scheduled else None, counts)
+                     self.bin_order.data_ptr() if self.scheduled else None, counts, shape)
 
     def radial(self) -> B.Radial:
         return B.Radial(self.n_bins, self.centre0, self.bin_width, self.rcoord.data_ptr())
@@ -178,6 +180,59 @@ def sigma_clip(frames, geom: Geometry, params: Params, out=None, norm=None, mask
     B.check("ss_sigma_clip", fn(_p(frames), _p(norm), _p(mask), F, ctypes.byref(geom.csr()),
                                 ctypes.byref(params.c()), ctypes.byref(profile_c(out)), _stream()))
     return out
+
+
+def sigma_clip_batches(batches, params: Params, outs=None):
+    """Clipped profiles of several batches with their own geometries in one
+    launch per row-length class: ``batches`` is a list of (frames [F, N],
+    Geometry); returns one profile dict per batch."""
+    outs = [new_profile(f.shape[0], g.n_bins, f.device) for f, g in batches] if outs is None else outs
+    keep = []   # the ctypes structs must outlive the call
+    arr = (B.ClipBatch * len(batches))()
+    for i, ((frames, geom), out) in enumerate(zip(batches, outs)):
+        _need_device(frames)
+        csr, prof = geom.csr(), profile_c(out)
+        keep += [csr, prof]
+        norm = geom.norm if params.error_model != "azimuthal" else None
+        arr[i] = B.ClipBatch(frames.data_ptr(), None if norm is None else norm.data_ptr(), frames.shape[0],
+                             ctypes.addressof(csr), ctypes.addressof(prof))
+    B.check("ss_sigma_clip_batches", B.lib().ss_sigma_clip_batches(arr, len(batches), ctypes.byref(params.c()),
+                                                                   _stream()))
+    return outs
+
+
+def autotune(batches, params: Params, reps=3, geometries=None):
+    """Pick, per row-length class, the fastest of the clip's work-group shapes
+    on the given batches (list of (frames, Geometry)), timing each variant
+    with HIP events on the current stream; the choice is stored in every
+    Geometry (``shape``) and returned with the timings (ms)."""
+    geoms = geometries or [g for _, g in batches]
+    n_var = 3
+    timings = {}
+    best = [0] * B.SS_N_CLASSES
+    stream = torch.cuda.current_stream()
+    outs = [new_profile(f.shape[0], g.n_bins, f.device) for f, g in batches]
+    for c in range(B.SS_N_CLASSES - 2):       # classes with alternative shapes
+        if not any(g.class_count[c] for g in geoms):
+            continue
+        row = []
+        for v in range(n_var):
+            for g in geoms:
+                g.shape[c] = v
+            # time this class alone: the other classes are held at their choice
+            sigma_clip_batches(batches, params, outs)
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            for _ in range(reps):
+                sigma_clip_batches(batches, params, outs)
+            b.record(stream)
+            b.synchronize()
+            row.append(a.elapsed_time(b) / reps)
+        best[c] = int(np.argmin(row))
+        timings[c] = row
+        for g in geoms:
+            g.shape[c] = best[c]
+    return best, timings
 
 
 def integrate(frames, geom: Geometry, params: Params, out=None, norm=None, mask=None):

@@ -22,7 +22,8 @@ SS_RC_MASKED = 0xFFFFFFFF
 SS_MAX_BINS = 4094
 SS_MAX_ITER = 32
 SS_MAX_PATCH = 15
-SS_N_CLASSES = 7
+SS_N_CLASSES = 8
+SS_SURROGATE_MAX_CLASS = 5
 SS_MLP_IN, SS_MLP_HID, SS_MLP_OUT = 19, 64, 2
 SS_MLP_K1, SS_MLP_OUT_PAD = 32, 16
 SS_MLP_OFF_W1, SS_MLP_OFF_B1, SS_MLP_OFF_W2 = 0, 2048, 2112
@@ -35,7 +36,7 @@ EXPORTED = (
     "ss_integrate", "ss_sigma_clip", "ss_classify_workspace", "ss_classify",
     "ss_compress", "ss_peakfind",
     "ss_clip_features", "ss_surrogate_targets", "ss_mlp_forward", "ss_mlp_grad_workspace", "ss_mlp_grad",
-    "ss_mlp_adam", "ss_sigma_clip_surrogate",
+    "ss_mlp_adam", "ss_sigma_clip_surrogate", "ss_sigma_clip_batches",
 )
 
 
@@ -49,7 +50,12 @@ class Csr(ctypes.Structure):
     _fields_ = [("n_bins", ctypes.c_int32), ("max_row", ctypes.c_int32), ("n_pix", ctypes.c_int64),
                 ("nnz", ctypes.c_int64), ("indptr", ctypes.c_void_p), ("indices", ctypes.c_void_p),
                 ("weight", ctypes.c_void_p), ("bin_order", ctypes.c_void_p),
-                ("class_count", ctypes.c_int32 * SS_N_CLASSES)]
+                ("class_count", ctypes.c_int32 * SS_N_CLASSES), ("shape", ctypes.c_int32 * SS_N_CLASSES)]
+
+
+class ClipBatch(ctypes.Structure):
+    _fields_ = [("frames", ctypes.c_void_p), ("norm", ctypes.c_void_p), ("n_frames", ctypes.c_int32),
+                ("csr", ctypes.c_void_p), ("out", ctypes.c_void_p)]
 
 
 class Params(ctypes.Structure):
@@ -133,6 +139,8 @@ def lib():
         L.ss_mlp_adam.argtypes = [vp, vp, vp, vp, i32, f32, f32, f32, f32, vp, vp]
         L.ss_sigma_clip_surrogate.restype = ctypes.c_int
         L.ss_sigma_clip_surrogate.argtypes = [vp, vp, vp, i32, P(Csr), P(Params), vp, f32, P(Profile), vp, vp]
+        L.ss_sigma_clip_batches.restype = ctypes.c_int
+        L.ss_sigma_clip_batches.argtypes = [vp, i32, P(Params), vp]
         _lib = L
     return _lib
 

@@ -25,6 +25,7 @@
 #include <hip/hip_fp16.h>
 
 #include <cmath>
+#include <vector>
 
 #include "common.h"
 
@@ -453,8 +454,11 @@ __device__ inline bool surrogate_stage(const ClipArgs &a, float2v (&vp)[FB][EPT 
     return false;
 }
 
-template <int BLOCK, int EPT, int FB, int WPE, int MODE>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) void k_clip_regs(ClipArgs a) {
+// The register clip of one (frame group, bin).  WLDS: the row's weights are
+// staged in LDS (rows up to 24 576 entries); otherwise they are read again
+// from memory (L2) where needed, for the longest rows.
+template <int BLOCK, int EPT, int FB, int MODE, bool WLDS>
+__device__ __forceinline__ void clip_body(const ClipArgs &a, int g, int bin) {
     constexpr int NW = BLOCK / kWave;
     constexpr int FPW = (FB + NW - 1) / NW;  // frames finished per wave
     static_assert(FB >= 1 && BLOCK % kWave == 0, "whole waves, at least one frame");
@@ -466,7 +470,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) vo
     __shared__ Surrogate sur_s[FB];
     __shared__ uint16_t wts_s[SUR ? SS_MLP_PARAMS : 2];
     __shared__ float h1_s[SUR ? FB : 1][SS_MLP_HID];
-    __shared__ float w_s[EPT * BLOCK];
+    __shared__ float w_s[WLDS ? EPT * BLOCK : 1];
     __shared__ float2 rem_s[NW][FB][kRemCap];
     __shared__ int cnt_s[NW][FB];
     __shared__ int more_s[NW];
@@ -476,8 +480,6 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) vo
     __shared__ double wstat[FB][NW][NWSTAT];
     __shared__ PassCtl ctl[FB];
 
-    int g, bin;
-    if (!block_item(a, FB, g, bin)) return;
     const int f0 = g * FB;
     const int nf = min(FB, a.n_frames - f0);
     const int tid = threadIdx.x;
@@ -524,6 +526,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) vo
         rf[f] = buffer_rsrc(fr, real ? uint32_t(a.n_pix) * 4u : 0u);
     }
     const uint32_t tofs = uint32_t(tid) * 4u;
+    // weight of slot e: from LDS, or again from memory for the longest rows
+#define SS_W(e) (WLDS ? w_s[(e) * BLOCK + tid] : buffer_load_f32(rw, tofs, uint32_t((e) * BLOCK) * 4u))
 
     // Values are held in pairs: float64 operands need even-aligned register
     // pairs, and single floats scattered over odd registers would leave the
@@ -546,7 +550,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) vo
             for (int e = 0; e < EPT; ++e) ix[e] = buffer_load_i32(ri, tofs, uint32_t(e * BLOCK) * 4u);
 #pragma unroll
             for (int e = 0; e < EPT; ++e) {
-                w_s[e * BLOCK + tid] = wt[e];
+                if constexpr (WLDS) w_s[e * BLOCK + tid] = wt[e];
                 const bool ok = (e * BLOCK + tid < len) && wt[e] > 0.0f && uint32_t(ix[e]) <= last;
                 ok_entry |= uint64_t(ok) << e;
             }
@@ -574,7 +578,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) vo
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
             const bool entry_ok = (uint32_t(ok_entry >> e) & 1u) != 0;
-            const float w = w_s[e * BLOCK + tid];
+            const float w = SS_W(e);
 #pragma unroll
             for (int f = 0; f < FB; ++f) {
                 const float x = SS_V(f, e);
@@ -618,7 +622,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) vo
         for (int q = 0; q < 4 * FB; ++q) t[q] = 0.0;
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
-            const float w = w_s[e * BLOCK + tid];
+            const float w = SS_W(e);
 #pragma unroll
             for (int f = 0; f < FB; ++f) {
                 const float x = SS_V(f, e);
@@ -719,7 +723,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) vo
 #pragma unroll
             for (int e = 0; e < EPT; ++e)
                 if (SS_V(f, e) == SS_V(f, e) && !(SUR && ((gone[f] >> e) & 1u)))
-                    add_member(t, double(w_s[e * BLOCK + tid]), double(SS_V(f, e)) - Kn, 0.0);
+                    add_member(t, double(SS_W(e)), double(SS_V(f, e)) - Kn, 0.0);
             block_sum<NSUM, BLOCK>(t, part, tot);
             if (tid == 0) {
                 t[S_N] = rint(t[S_N]);
@@ -760,7 +764,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) vo
                             continue;
                         }
                         if (out) {
-                            rem_s[wid][f][used + lanes_below(m)] = make_float2(w_s[e * BLOCK + tid], SS_V(f, e));
+                            rem_s[wid][f][used + lanes_below(m)] = make_float2(SS_W(e), SS_V(f, e));
                             if constexpr (SUR)
                                 gone[f] |= uint64_t(1) << e;  // the value stays for the final check
                             else
@@ -857,6 +861,42 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) vo
             }
         }
     }
+#undef SS_W
+}
+
+template <int BLOCK, int EPT, int FB, int WPE, int MODE, bool WLDS>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) void k_clip_regs(ClipArgs a) {
+    int g, bin;
+    if (!block_item(a, FB, g, bin)) return;
+    clip_body<BLOCK, EPT, FB, MODE, WLDS>(a, g, bin);
+}
+
+// Several batches, each with its own geometry, in one launch per row-length
+// class: the items (frame group, bin) of every batch's bins of the class,
+// batch after batch, mapped to work-groups as block_item does.
+constexpr int kMaxJobs = 8;
+
+struct MultiArgs {
+    int32_t n_jobs;
+    uint32_t base[kMaxJobs + 1];  // first item of each batch; base[n_jobs] = all items
+    ClipArgs job[kMaxJobs];
+};
+
+template <int BLOCK, int EPT, int FB, int WPE, bool WLDS>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) void k_clip_regs_multi(MultiArgs m) {
+    const uint32_t total = m.base[m.n_jobs];
+    const uint32_t per = (total + 7u) / 8u;
+    const uint32_t gb = blockIdx.x;
+    const uint32_t item = (gb % 8u) * per + gb / 8u;
+    if (gb / 8u >= per || item >= total) return;
+    int j = 0;
+    while (j + 1 < m.n_jobs && item >= m.base[j + 1]) ++j;
+    const ClipArgs &a = m.job[j];
+    const uint32_t local = item - m.base[j];
+    const uint32_t nb = uint32_t(a.launch_bins);
+    const int bin = a.bin_order ? a.bin_order[a.order_base + int(local % nb)] : int(local % nb);
+    if (uint32_t(bin) >= uint32_t(a.n_bins)) return;
+    clip_body<BLOCK, EPT, FB, MODE_CLIP, WLDS>(a, int(local / nb), bin);
 }
 #undef SS_V
 
@@ -971,10 +1011,10 @@ __global__ __launch_bounds__(BLOCK) void k_clip_stream(ClipArgs a) {
 
 // ---------------------------------------------------------------------------
 
-template <int BLOCK, int EPT, int FB, int WPE, int MODE>
+template <int BLOCK, int EPT, int FB, int WPE, int MODE, bool WLDS>
 void launch_regs(const ClipArgs &a, hipStream_t stream) {
     const int64_t groups = (int64_t(a.n_frames) + FB - 1) / FB;
-    k_clip_regs<BLOCK, EPT, FB, WPE, MODE><<<dim3(item_grid(groups * a.launch_bins)), BLOCK, 0, stream>>>(a);
+    k_clip_regs<BLOCK, EPT, FB, WPE, MODE, WLDS><<<dim3(item_grid(groups * a.launch_bins)), BLOCK, 0, stream>>>(a);
 }
 
 template <int BLOCK>
@@ -982,57 +1022,123 @@ void launch_stream(const ClipArgs &a, hipStream_t stream) {
     k_clip_stream<BLOCK><<<dim3(item_grid(int64_t(a.n_frames) * a.launch_bins)), BLOCK, 0, stream>>>(a);
 }
 
-// Work-group shape of row-length class c (rows up to ss_class_rows(c)):
-// threads, values per thread, frames per work-group and the waves per SIMD
-// the register budget is set for; batches use the first shape, single
-// frames the second.
-#ifndef SS_CLIP_C0
-#define SS_CLIP_C0 256, 4, 4, 4
-#endif
-#ifndef SS_CLIP_C1
-#define SS_CLIP_C1 256, 8, 4, 4
-#endif
-#ifndef SS_CLIP_C2
-#define SS_CLIP_C2 256, 16, 2, 4
-#endif
-#ifndef SS_CLIP_C3
-#define SS_CLIP_C3 256, 32, 1, 4
-#endif
-#ifndef SS_CLIP_C4
-#define SS_CLIP_C4 512, 32, 1, 4
-#endif
-#ifndef SS_CLIP_C5
-#define SS_CLIP_C5 1024, 24, 2, 4
-#endif
-#define SS_CLIP_C0_SINGLE 256, 4, 1, 5
-#define SS_CLIP_C1_SINGLE 256, 8, 1, 5
-#define SS_CLIP_C2_SINGLE 128, 32, 1, 4
-#define SS_CLIP_C3_SINGLE 256, 32, 1, 4
-#define SS_CLIP_C4_SINGLE 512, 32, 1, 4
-#define SS_CLIP_C5_SINGLE 1024, 24, 1, 4
+// Shapes of the register kernel: threads, values per thread, frames per
+// work-group, waves per SIMD the register budget is set for, and whether the
+// weights sit in LDS.  Per row-length class (rows up to ss_class_rows(c)):
+// variant 0 is the default for batches, 1 and 2 the alternatives the
+// autotuner may pick (plain clip of batches only); single frames use the
+// SINGLE shape.  Measured on gfx950: more independent work-groups per CU
+// hide the gather latency better than more frames per work-group.
+//   class  rows     variant 0        variant 1        variant 2
+//   0      1024     256 x 4,  4 fr   128 x 8,  2 fr   256 x 4,  2 fr
+//   1      2048     256 x 8,  4 fr   128 x 16, 2 fr   256 x 8,  2 fr
+//   2      4096     256 x 16, 2 fr   128 x 32, 1 fr   256 x 16, 1 fr
+//   3      8192     256 x 32, 1 fr   512 x 16, 2 fr   1024 x 8, 4 fr
+//   4      16384    512 x 32, 1 fr   1024 x 16, 2 fr  512 x 32, 2 fr
+//   5      24576    1024 x 24, 2 fr  1024 x 24, 1 fr  512 x 48, 1 fr
+//   6      51200    1024 x 50, 1 fr, weights read again from memory
+//   7      longer   the streaming kernel
 
-template <int ROWS, int BLOCK, int EPT, int FB, int WPE>
+template <int ROWS, int BLOCK, int EPT, int FB, int WPE, bool WLDS = true>
 void launch_shape(const ClipArgs &a, int mode, hipStream_t stream) {
     static_assert(BLOCK * EPT >= ROWS, "a work-group holds the longest row of its class");
     switch (mode) {
-        case MODE_FEATURES: launch_regs<BLOCK, EPT, FB, WPE, MODE_FEATURES>(a, stream); break;
-        case MODE_SURROGATE: launch_regs<BLOCK, EPT, FB, WPE, MODE_SURROGATE>(a, stream); break;
-        default: launch_regs<BLOCK, EPT, FB, WPE, MODE_CLIP>(a, stream); break;
+        case MODE_FEATURES: launch_regs<BLOCK, EPT, FB, WPE, MODE_FEATURES, WLDS>(a, stream); break;
+        case MODE_SURROGATE: launch_regs<BLOCK, EPT, FB, WPE, MODE_SURROGATE, WLDS>(a, stream); break;
+        default: launch_regs<BLOCK, EPT, FB, WPE, MODE_CLIP, WLDS>(a, stream); break;
     }
 }
 
-// (the streaming kernel serves the plain clip only; the surrogate entry
-// points refuse rows beyond class 5 before launching)
-void launch_class(const ClipArgs &a, int c, int mode, hipStream_t stream) {
+template <int ROWS, int BLOCK, int EPT, int FB, int WPE, bool WLDS = true>
+void launch_plain(const ClipArgs &a, hipStream_t stream) {
+    static_assert(BLOCK * EPT >= ROWS, "a work-group holds the longest row of its class");
+    launch_regs<BLOCK, EPT, FB, WPE, MODE_CLIP, WLDS>(a, stream);
+}
+
+// (the surrogate modes use variant 0 of classes 0-5 only; the surrogate
+// entry points refuse longer rows before launching)
+void launch_class(const ClipArgs &a, int c, int variant, int mode, hipStream_t stream) {
     const bool batch = a.n_frames > 1;
-    switch (c) {
-        case 0: batch ? launch_shape<1024, SS_CLIP_C0>(a, mode, stream) : launch_shape<1024, SS_CLIP_C0_SINGLE>(a, mode, stream); break;
-        case 1: batch ? launch_shape<2048, SS_CLIP_C1>(a, mode, stream) : launch_shape<2048, SS_CLIP_C1_SINGLE>(a, mode, stream); break;
-        case 2: batch ? launch_shape<4096, SS_CLIP_C2>(a, mode, stream) : launch_shape<4096, SS_CLIP_C2_SINGLE>(a, mode, stream); break;
-        case 3: batch ? launch_shape<8192, SS_CLIP_C3>(a, mode, stream) : launch_shape<8192, SS_CLIP_C3_SINGLE>(a, mode, stream); break;
-        case 4: batch ? launch_shape<16384, SS_CLIP_C4>(a, mode, stream) : launch_shape<16384, SS_CLIP_C4_SINGLE>(a, mode, stream); break;
-        case 5: batch ? launch_shape<24576, SS_CLIP_C5>(a, mode, stream) : launch_shape<24576, SS_CLIP_C5_SINGLE>(a, mode, stream); break;
-        default: launch_stream<1024>(a, stream); break;
+    if (c == 6) {
+        launch_plain<51200, 1024, 50, 1, 4, false>(a, stream);
+        return;
+    }
+    if (c > 6) {
+        launch_stream<1024>(a, stream);
+        return;
+    }
+    if (!batch) {
+        switch (c) {
+            case 0: launch_shape<1024, 256, 4, 1, 5>(a, mode, stream); break;
+            case 1: launch_shape<2048, 256, 8, 1, 5>(a, mode, stream); break;
+            case 2: launch_shape<4096, 128, 32, 1, 4>(a, mode, stream); break;
+            case 3: launch_shape<8192, 256, 32, 1, 4>(a, mode, stream); break;
+            case 4: launch_shape<16384, 512, 32, 1, 4>(a, mode, stream); break;
+            default: launch_shape<24576, 1024, 24, 1, 4>(a, mode, stream); break;
+        }
+        return;
+    }
+    if (mode != MODE_CLIP || variant < 0 || variant > 2) variant = 0;
+    switch (c * 3 + variant) {
+        case 0: launch_shape<1024, 256, 4, 4, 4>(a, mode, stream); break;
+        case 1: launch_plain<1024, 128, 8, 2, 4>(a, stream); break;
+        case 2: launch_plain<1024, 256, 4, 2, 4>(a, stream); break;
+        case 3: launch_shape<2048, 256, 8, 4, 4>(a, mode, stream); break;
+        case 4: launch_plain<2048, 128, 16, 2, 4>(a, stream); break;
+        case 5: launch_plain<2048, 256, 8, 2, 4>(a, stream); break;
+        case 6: launch_shape<4096, 256, 16, 2, 4>(a, mode, stream); break;
+        case 7: launch_plain<4096, 128, 32, 1, 4>(a, stream); break;
+        case 8: launch_plain<4096, 256, 16, 1, 5>(a, stream); break;
+        case 9: launch_shape<8192, 256, 32, 1, 4>(a, mode, stream); break;
+        case 10: launch_plain<8192, 512, 16, 2, 4>(a, stream); break;
+        case 11: launch_plain<8192, 1024, 8, 4, 4>(a, stream); break;
+        case 12: launch_shape<16384, 512, 32, 1, 4>(a, mode, stream); break;
+        case 13: launch_plain<16384, 1024, 16, 2, 4>(a, stream); break;
+        case 14: launch_plain<16384, 512, 32, 2, 2>(a, stream); break;
+        case 15: launch_shape<24576, 1024, 24, 2, 4>(a, mode, stream); break;
+        case 16: launch_plain<24576, 1024, 24, 1, 4>(a, stream); break;
+        default: launch_plain<24576, 512, 48, 1, 2>(a, stream); break;
+    }
+}
+
+// One launch per class over several batches (plain clip, batches of > 1 frame).
+template <int ROWS, int BLOCK, int EPT, int FB, int WPE, bool WLDS = true>
+void launch_multi(MultiArgs &m, hipStream_t stream) {
+    static_assert(BLOCK * EPT >= ROWS, "a work-group holds the longest row of its class");
+    m.base[0] = 0;
+    for (int j = 0; j < m.n_jobs; ++j) {
+        const int64_t groups = (int64_t(m.job[j].n_frames) + FB - 1) / FB;
+        m.base[j + 1] = m.base[j] + uint32_t(groups * m.job[j].launch_bins);
+    }
+    if (m.base[m.n_jobs] == 0) return;
+    k_clip_regs_multi<BLOCK, EPT, FB, WPE, WLDS><<<dim3(item_grid(m.base[m.n_jobs])), BLOCK, 0, stream>>>(m);
+}
+
+void launch_class_multi(MultiArgs &m, int c, int variant, hipStream_t stream) {
+    if (variant < 0 || variant > 2) variant = 0;
+    if (c == 6) {
+        launch_multi<51200, 1024, 50, 1, 4, false>(m, stream);
+        return;
+    }
+    switch (c * 3 + variant) {
+        case 0: launch_multi<1024, 256, 4, 4, 4>(m, stream); break;
+        case 1: launch_multi<1024, 128, 8, 2, 4>(m, stream); break;
+        case 2: launch_multi<1024, 256, 4, 2, 4>(m, stream); break;
+        case 3: launch_multi<2048, 256, 8, 4, 4>(m, stream); break;
+        case 4: launch_multi<2048, 128, 16, 2, 4>(m, stream); break;
+        case 5: launch_multi<2048, 256, 8, 2, 4>(m, stream); break;
+        case 6: launch_multi<4096, 256, 16, 2, 4>(m, stream); break;
+        case 7: launch_multi<4096, 128, 32, 1, 4>(m, stream); break;
+        case 8: launch_multi<4096, 256, 16, 1, 5>(m, stream); break;
+        case 9: launch_multi<8192, 256, 32, 1, 4>(m, stream); break;
+        case 10: launch_multi<8192, 512, 16, 2, 4>(m, stream); break;
+        case 11: launch_multi<8192, 1024, 8, 4, 4>(m, stream); break;
+        case 12: launch_multi<16384, 512, 32, 1, 4>(m, stream); break;
+        case 13: launch_multi<16384, 1024, 16, 2, 4>(m, stream); break;
+        case 14: launch_multi<16384, 512, 32, 2, 2>(m, stream); break;
+        case 15: launch_multi<24576, 1024, 24, 2, 4>(m, stream); break;
+        case 16: launch_multi<24576, 1024, 24, 1, 4>(m, stream); break;
+        default: launch_multi<24576, 512, 48, 1, 2>(m, stream); break;
     }
 }
 
@@ -1060,7 +1166,8 @@ void dispatch(ClipArgs a, const ss_csr *csr, int n_frames, int mode, hipStream_t
         a.bin_order = nullptr;
         a.order_base = 0;
         a.launch_bins = a.n_bins;
-        launch_class(a, class_of(csr->max_row), mode, stream);
+        const int c = class_of(csr->max_row);
+        launch_class(a, c, csr->shape[c], mode, stream);
         return;
     }
     int32_t base = 0;
@@ -1070,7 +1177,7 @@ void dispatch(ClipArgs a, const ss_csr *csr, int n_frames, int mode, hipStream_t
         a.bin_order = csr->bin_order;
         a.order_base = base;
         a.launch_bins = cnt;
-        launch_class(a, c, mode, stream);
+        launch_class(a, c, csr->shape[c], mode, stream);
         base += cnt;
     }
 }
@@ -1089,9 +1196,12 @@ struct SurrogateIo {
     int32_t *accepted = nullptr;
 };
 
-int clip_entry(const float *frames, const float *norm, const uint8_t *mask, int32_t n_frames, const ss_csr *csr,
-               const ss_params *p, const ss_profile *out, bool integrate_only, const SurrogateIo &io,
-               hipStream_t stream) {
+// Checks one call's arguments and fills the kernel arguments; returns an
+// error code, or SS_OK with `empty` set when there is nothing to launch.
+int clip_args(const float *frames, const float *norm, const uint8_t *mask, int32_t n_frames, const ss_csr *csr,
+              const ss_params *p, const ss_profile *out, bool integrate_only, const SurrogateIo &io, ss::ClipArgs &a,
+              bool &empty) {
+    empty = true;
     const bool features = io.mode == ss::MODE_FEATURES;
     if (!csr || !p || (!features && !out)) return SS_EINVAL;
     if (n_frames < 0) return SS_ESIZE;
@@ -1104,7 +1214,7 @@ int clip_entry(const float *frames, const float *norm, const uint8_t *mask, int3
         return SS_EINVAL;
     if (io.mode != ss::MODE_CLIP) {
         // the surrogate runs in the register kernel only
-        if (mask || csr->max_row > ss_class_rows(SS_N_CLASSES - 2) || csr->n_pix >= (int64_t(1) << 30))
+        if (mask || csr->max_row > ss_class_rows(SS_SURROGATE_MAX_CLASS) || csr->n_pix >= (int64_t(1) << 30))
             return SS_EINVAL;
         if (features && (!io.features || !io.stats0)) return SS_EINVAL;
         if (io.mode == ss::MODE_SURROGATE &&
@@ -1113,6 +1223,7 @@ int clip_entry(const float *frames, const float *norm, const uint8_t *mask, int3
             return SS_EINVAL;
     }
     if (n_frames == 0) return SS_OK;
+    empty = false;
     if (csr->n_pix == 0 && csr->nnz > 0) return SS_ESIZE;
     if (!frames || !csr->indptr || (csr->nnz > 0 && (!csr->indices || !csr->weight)))
         return SS_EINVAL;
@@ -1121,7 +1232,7 @@ int clip_entry(const float *frames, const float *norm, const uint8_t *mask, int3
         return SS_EINVAL;
     const int64_t items = int64_t(csr->n_bins) * n_frames;
     if (items >= (int64_t(1) << 31) - 8) return SS_ESIZE;
-    ss::ClipArgs a{};
+    a = ss::ClipArgs{};
     a.frames = frames;
     a.n_pix = csr->n_pix;
     a.norm = norm;
@@ -1160,8 +1271,20 @@ int clip_entry(const float *frames, const float *norm, const uint8_t *mask, int3
             sum += csr->class_count[c];
         }
         if (sum != csr->n_bins) return SS_EINVAL;
-        if (io.mode != ss::MODE_CLIP && csr->class_count[SS_N_CLASSES - 1] != 0) return SS_EINVAL;
+        if (io.mode != ss::MODE_CLIP)
+            for (int c = SS_SURROGATE_MAX_CLASS + 1; c < SS_N_CLASSES; ++c)
+                if (csr->class_count[c] != 0) return SS_EINVAL;
     }
+    return SS_OK;
+}
+
+int clip_entry(const float *frames, const float *norm, const uint8_t *mask, int32_t n_frames, const ss_csr *csr,
+               const ss_params *p, const ss_profile *out, bool integrate_only, const SurrogateIo &io,
+               hipStream_t stream) {
+    ss::ClipArgs a;
+    bool empty = true;
+    const int rc = clip_args(frames, norm, mask, n_frames, csr, p, out, integrate_only, io, a, empty);
+    if (rc != SS_OK || empty) return rc;
     ss::dispatch(a, csr, n_frames, io.mode, stream);
     if (io.mode == ss::MODE_SURROGATE) {
         // the groups holding a refused bin, clipped again from scratch
@@ -1209,4 +1332,56 @@ extern "C" int ss_sigma_clip_surrogate(const float *frames, const float *norm, c
     io.widen = widen;
     io.accepted = accepted;
     return clip_entry(frames, norm, mask, n_frames, csr, params, out, false, io, stream);
+}
+
+extern "C" int ss_sigma_clip_batches(const ss_clip_batch *batches, int32_t n_batches, const ss_params *params,
+                                     hipStream_t stream) {
+    if (n_batches < 0) return SS_ESIZE;
+    if (n_batches == 0) return SS_OK;
+    if (!batches || !params) return SS_EINVAL;
+    std::vector<ss::ClipArgs> args(static_cast<size_t>(n_batches));
+    std::vector<char> shared(static_cast<size_t>(n_batches), 0);
+    for (int32_t b = 0; b < n_batches; ++b) {
+        const ss_clip_batch &x = batches[b];
+        bool empty = true;
+        const int rc = clip_args(x.frames, x.norm, nullptr, x.n_frames, x.csr, params, x.out, false, SurrogateIo{},
+                                 args[size_t(b)], empty);
+        if (rc != SS_OK) return rc;
+        // shared launches: azimuthal model, scheduled CSR, batches of frames
+        shared[size_t(b)] = !empty && params->error_model == SS_AZIMUTHAL && x.csr->bin_order != nullptr &&
+                            x.n_frames > 1 && x.csr->n_pix < (int64_t(1) << 30);
+    }
+    const int32_t *shape = batches[0].csr->shape;
+    for (int32_t b = 0; b < n_batches; ++b)
+        if (!shared[size_t(b)] && batches[b].n_frames > 0)
+            ss::dispatch(args[size_t(b)], batches[b].csr, batches[b].n_frames, ss::MODE_CLIP, stream);
+    for (int c = SS_N_CLASSES - 1; c >= 0; --c) {
+        ss::MultiArgs m{};
+        auto flush = [&]() {
+            if (m.n_jobs == 0) return;
+            if (c == SS_N_CLASSES - 1) {
+                for (int j = 0; j < m.n_jobs; ++j) ss::launch_stream<1024>(m.job[j], stream);
+            } else {
+                ss::launch_class_multi(m, c, shape[c], stream);
+            }
+            m.n_jobs = 0;
+        };
+        for (int32_t b = 0; b < n_batches; ++b) {
+            if (!shared[size_t(b)]) continue;
+            const ss_csr *csr = batches[b].csr;
+            const int32_t cnt = csr->class_count[c];
+            if (cnt <= 0) continue;
+            int32_t base = 0;
+            for (int c2 = SS_N_CLASSES - 1; c2 > c; --c2) base += csr->class_count[c2];
+            ss::ClipArgs a = args[size_t(b)];
+            a.bin_order = csr->bin_order;
+            a.order_base = base;
+            a.launch_bins = cnt;
+            m.job[m.n_jobs++] = a;
+            if (m.n_jobs == ss::kMaxJobs) flush();
+        }
+        flush();
+    }
+    SS_RETURN_IF_LAUNCH_FAILED();
+    return SS_OK;
 }

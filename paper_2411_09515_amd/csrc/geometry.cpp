@@ -166,7 +166,7 @@ extern "C" int ss_radial_coords(int32_t height, int32_t width, double pixel_m, d
 namespace {
 // Longest row of each class but the last (which takes any length); the clip
 // sizes its work-groups to these (work-group threads x values per thread).
-constexpr int32_t kClassRows[SS_N_CLASSES - 1] = {1024, 2048, 4096, 8192, 16384, 24576};
+constexpr int32_t kClassRows[SS_N_CLASSES - 1] = {1024, 2048, 4096, 8192, 16384, 24576, 51200};
 }  // namespace
 
 extern "C" int32_t ss_class_rows(int32_t c) {

@@ -260,6 +260,17 @@ def training_frame(geom: Geometry, frame_idx: int):
     return word, info
 
 
+def uneven_frame(geom: Geometry, frame_idx: int, hit_rate: float = 0.3, max_spots: int = 500):
+    """One raw frame of the batched mixed-detector workload, from a seed
+    stream of its own: a hit with probability ``hit_rate`` holding
+    1..``max_spots`` spots, otherwise background only."""
+    rng = np.random.default_rng(np.random.SeedSequence([geom.config_id, 2_000_000 + frame_idx]))
+    n_spots = int(rng.integers(1, max_spots + 1)) if rng.random() < hit_rate else 0
+    spots, truth = spot_expectation(rng, geom, stripe_mask(geom), n_spots)
+    photons = rng.poisson(_expected_background(geom) + spots).astype(np.float64)
+    return _encode(geom, rng, photons, truth)
+
+
 def _encode(geom: Geometry, rng: np.random.Generator, photons: np.ndarray, truth):
     ped, gain = jungfrau_calibration(geom)
     e = photons.reshape(-1)
