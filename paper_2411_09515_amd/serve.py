@@ -1,0 +1,274 @@
+"""Continuous-batching service of frames from several detectors.
+
+Frames arrive from each detector into a device-resident ingest ring (as a
+detector writing straight into GPU memory would deliver them) and are served
+to completion: corrected, clipped, sparsified and peak-picked (the whole
+path), with the kept pixels, the peaks and the profile returned to the host.
+
+Scheduling:
+* every detector owns a set of *slots*, each the device memory of one
+  in-flight batch (frames, profile, workspace, outputs), and one stream
+  (default priority); the number of slots comes from an HBM budget
+  (admission by memory);
+* whenever a slot is free and its detector has frames waiting, the waiting
+  frames (up to the slot's batch size) are admitted as one batch and
+  launched at once, while other batches are still running: batches of
+  different detectors, and successive batches of one detector, overlap on
+  the device;
+* a batch completes in two steps: the per-frame counts come back, then
+  exactly the kept pixels and peaks; the slot is then free again.
+
+Per-frame latency is measured from the frame's arrival to the moment its
+results are on the host.  Every step of the path runs in the library's HIP
+kernels; this module only schedules them.
+"""
+
+from __future__ import annotations
+
+import collections
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import api
+from . import binding as B
+
+
+@dataclass
+class Request:
+    """One frame: detector, index of its raw frame in the detector's ingest
+    ring, arrival time (s, on the server's clock)."""
+
+    det: int
+    ring_index: int
+    t_arrival: float
+    rid: int = 0
+    t_done: float = float("nan")
+    batch_size: int = 0
+    n_kept: int = 0
+    kept_index: np.ndarray = field(default=None, repr=False)
+    kept_value: np.ndarray = field(default=None, repr=False)
+    n_peaks: int = 0
+    peaks: np.ndarray = field(default=None, repr=False)
+    mean: np.ndarray = field(default=None, repr=False)
+    std: np.ndarray = field(default=None, repr=False)
+
+
+class Detector:
+    """A detector's resident state: geometry, calibration, ingest ring."""
+
+    def __init__(self, name, geom: api.Geometry, pedestal, gain, ring_raw, params: api.Params, max_batch=8,
+                 kept_capacity=None, peak_capacity=4096):
+        self.name, self.geom, self.params = name, geom, params
+        self.pedestal, self.gain = pedestal, gain
+        self.ring = ring_raw            # device [K, N] raw words (int16 view of uint16)
+        self.max_batch = int(max_batch)
+        # kept pixels per frame: 1/16 of the detector by default (about 1.8 % are kept at 3 sigma)
+        self.kept_capacity = int(geom.n_pix // 16 if kept_capacity is None else kept_capacity)
+        self.peak_capacity = int(peak_capacity)
+
+    def slot_bytes(self):
+        N, nb, B_ = self.geom.n_pix, self.geom.n_bins, self.max_batch
+        ws = api.workspace_bytes(B_, N, nb)
+        per = N * (2 + 4) + nb * (4 * 8 + 3 * 4) + self.kept_capacity * 8 + self.peak_capacity * B.PEAK_BYTES + 16
+        return B_ * per + ws
+
+
+class _Slot:
+    def __init__(self, det: Detector, device, stream):
+        F, N, nb = det.max_batch, det.geom.n_pix, det.geom.n_bins
+        self.det = det
+        self.raw = torch.empty((F, N), dtype=torch.int16, device=device)
+        self.frames = torch.empty((F, N), dtype=torch.float32, device=device)
+        self.n_invalid = torch.empty(F, dtype=torch.int64, device=device)
+        self.profile = api.new_profile(F, nb, device)
+        self.workspace = api.new_workspace(F, det.geom, device)
+        self.out = dict(kept_index=torch.empty((F, det.kept_capacity), dtype=torch.int32, device=device),
+                        kept_value=torch.empty((F, det.kept_capacity), dtype=torch.float32, device=device),
+                        n_kept=torch.empty(F, dtype=torch.int64, device=device),
+                        peaks=torch.empty((F, det.peak_capacity, B.PEAK_BYTES), dtype=torch.uint8,
+                                          device=device),
+                        n_peaks=torch.empty(F, dtype=torch.int64, device=device))
+        self.h_idx = torch.empty(F, dtype=torch.int64, pin_memory=True)
+        self.d_idx = torch.empty(F, dtype=torch.int64, device=device)
+        self.h_counts = torch.empty((2, F), dtype=torch.int64, pin_memory=True)
+        self.h_mean = torch.empty((F, nb), dtype=torch.float64, pin_memory=True)
+        self.h_std = torch.empty((F, nb), dtype=torch.float64, pin_memory=True)
+        self.h_kept_index = torch.empty((F, det.kept_capacity), dtype=torch.int32, pin_memory=True)
+        self.h_kept_value = torch.empty((F, det.kept_capacity), dtype=torch.float32, pin_memory=True)
+        self.h_peaks = torch.empty((F, det.peak_capacity, B.PEAK_BYTES), dtype=torch.uint8, pin_memory=True)
+        self.stream = stream
+        self.ev_counts = torch.cuda.Event()
+        self.ev_done = torch.cuda.Event()
+        self.batch = []
+        self.phase = 0   # 0 free, 1 computing, 2 copying results
+
+
+class Server:
+    """Continuous batching over detectors within an HBM budget (bytes)."""
+
+    def __init__(self, detectors, hbm_budget=8 << 30, device="cuda", max_slots_per_detector=4):
+        self.detectors = list(detectors)
+        self.device = torch.device(device)
+        self.slots = []
+        # admission by memory: slots for each detector while the budget lasts,
+        # round robin so that every detector gets at least one
+        used = 0
+        per_det = [0] * len(self.detectors)
+        # one stream per detector: a detector's batches queue in order, different
+        # detectors' batches run side by side (the device has few hardware queues,
+        # so more streams than detectors would only make batches wait behind others)
+        self.streams = [torch.cuda.Stream(device=self.device) for _ in self.detectors]
+        progress = True
+        while progress:
+            progress = False
+            for i, d in enumerate(self.detectors):
+                b = d.slot_bytes()
+                if per_det[i] < max_slots_per_detector and used + b <= hbm_budget:
+                    self.slots.append(_Slot(d, self.device, self.streams[i]))
+                    per_det[i] += 1
+                    used += b
+                    progress = True
+        if any(n == 0 for n in per_det):
+            raise MemoryError("the HBM budget does not hold one batch of every detector")
+        self.slots_per_detector = per_det
+        self.reserved_bytes = used
+
+    # -- one batch -----------------------------------------------------------------------
+
+    def _launch(self, slot: _Slot, batch):
+        d = slot.det
+        F = len(batch)
+        for f, r in enumerate(batch):
+            slot.h_idx[f] = r.ring_index
+        with torch.cuda.stream(slot.stream):
+            slot.d_idx[:F].copy_(slot.h_idx[:F], non_blocking=True)
+            torch.index_select(d.ring, 0, slot.d_idx[:F], out=slot.raw[:F])
+            frames = slot.frames[:F]
+            api.correct(slot.raw[:F], d.pedestal, d.gain, d.geom.norm, out=frames, n_invalid=slot.n_invalid[:F])
+            prof = {k: v[:F] for k, v in slot.profile.items()}
+            api.sigma_clip(frames, d.geom, d.params, out=prof)
+            out = {k: v[:F] for k, v in slot.out.items()}
+            api.classify(frames, d.geom, prof, d.params, d.kept_capacity, d.peak_capacity,
+                         workspace=slot.workspace, out=out)
+            slot.h_counts[0, :F].copy_(out["n_kept"], non_blocking=True)
+            slot.h_counts[1, :F].copy_(out["n_peaks"], non_blocking=True)
+            slot.h_mean[:F].copy_(prof["mean"], non_blocking=True)
+            slot.h_std[:F].copy_(prof["std"], non_blocking=True)
+            slot.ev_counts.record(slot.stream)
+        slot.batch = batch
+        slot.phase = 1
+
+    def _fetch(self, slot: _Slot):
+        d = slot.det
+        F = len(slot.batch)
+        nk = np.minimum(slot.h_counts[0, :F].numpy(), d.kept_capacity)
+        npk = np.minimum(slot.h_counts[1, :F].numpy(), d.peak_capacity)
+        with torch.cuda.stream(slot.stream):
+            # contiguous row prefixes only: those copies stay asynchronous
+            for f in range(F):
+                if nk[f]:
+                    slot.h_kept_index[f, :nk[f]].copy_(slot.out["kept_index"][f, :nk[f]], non_blocking=True)
+                    slot.h_kept_value[f, :nk[f]].copy_(slot.out["kept_value"][f, :nk[f]], non_blocking=True)
+                if npk[f]:
+                    slot.h_peaks[f, :npk[f]].copy_(slot.out["peaks"][f, :npk[f]], non_blocking=True)
+            slot.ev_done.record(slot.stream)
+        slot.phase = 2
+
+    def _finish(self, slot: _Slot, now):
+        F = len(slot.batch)
+        counts = slot.h_counts[:, :F].numpy()
+        for f, r in enumerate(slot.batch):
+            nk = min(int(counts[0, f]), slot.det.kept_capacity)
+            npk = min(int(counts[1, f]), slot.det.peak_capacity)
+            r.n_kept, r.n_peaks = int(counts[0, f]), int(counts[1, f])
+            r.kept_index = slot.h_kept_index[f, :nk].numpy().view(np.uint32).copy()
+            r.kept_value = slot.h_kept_value[f, :nk].numpy().copy()
+            r.peaks = api.peaks_to_numpy(slot.h_peaks[f], npk)
+            r.mean = slot.h_mean[f].numpy().copy()
+            r.std = slot.h_std[f].numpy().copy()
+            r.batch_size = F
+            r.t_done = now
+        slot.batch = []
+        slot.phase = 0
+
+    def warmup(self):
+        """One batch of one frame and one full batch per detector, so that the
+        first served frames do not pay for loading kernels."""
+        reqs = []
+        for d_i, d in enumerate(self.detectors):
+            reqs.append(Request(det=d_i, ring_index=0, t_arrival=0.0))
+        self.run(reqs, realtime=False)
+        reqs = [Request(det=d_i, ring_index=k % d.ring.shape[0], t_arrival=0.0)
+                for d_i, d in enumerate(self.detectors) for k in range(d.max_batch)]
+        self.run(reqs, realtime=False)
+
+    # -- the loop ------------------------------------------------------------------------
+
+    def run(self, requests, realtime=True, idle_sleep=20e-6):
+        """Serve ``requests`` (sorted by arrival); with ``realtime`` a request is
+        visible only from its arrival time on.  Returns the requests, completed,
+        and a dict of run statistics."""
+        reqs = sorted(requests, key=lambda r: r.t_arrival)
+        for i, r in enumerate(reqs):
+            r.rid = i
+        waiting = [collections.deque() for _ in self.detectors]
+        det_index = {id(d): i for i, d in enumerate(self.detectors)}
+        nxt, done = 0, 0
+        max_wait, n_batches, max_busy = 0, 0, 0
+        t0 = time.perf_counter()
+        while done < len(reqs):
+            now = time.perf_counter() - t0
+            while nxt < len(reqs) and (not realtime or reqs[nxt].t_arrival <= now):
+                waiting[reqs[nxt].det].append(reqs[nxt])
+                nxt += 1
+            busy = False
+            for s in self.slots:
+                if s.phase == 1 and s.ev_counts.query():
+                    self._fetch(s)
+                    busy = True
+                if s.phase == 2 and s.ev_done.query():
+                    done += len(s.batch)
+                    self._finish(s, time.perf_counter() - t0)
+                    busy = True
+            for s in self.slots:
+                if s.phase != 0:
+                    continue
+                q = waiting[det_index[id(s.det)]]
+                if not q:
+                    continue
+                batch = [q.popleft() for _ in range(min(len(q), s.det.max_batch))]
+                self._launch(s, batch)
+                n_batches += 1
+                busy = True
+            max_wait = max(max_wait, sum(len(q) for q in waiting))
+            max_busy = max(max_busy, sum(1 for s in self.slots if s.phase != 0))
+            if not busy and idle_sleep:
+                time.sleep(idle_sleep)
+        wall = time.perf_counter() - t0
+        lat = np.array([r.t_done - r.t_arrival for r in reqs]) * 1e3
+        stats = dict(frames=len(reqs), wall_s=wall, batches=n_batches, max_waiting=max_wait,
+                     max_batches_in_flight=max_busy,
+                     mean_batch=len(reqs) / max(1, n_batches),
+                     latency_ms={"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                                 "max": float(lat.max())} if len(lat) else None,
+                     slots_per_detector=self.slots_per_detector, reserved_bytes=self.reserved_bytes)
+        return reqs, stats
+
+
+def poisson_arrivals(rates_hz, duration_s, ring_sizes, seed=0):
+    """Requests with Poisson arrivals per detector (rates in Hz) over
+    ``duration_s``; each request points at the next frame of its ring."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for d, (rate, k) in enumerate(zip(rates_hz, ring_sizes)):
+        t, n = 0.0, 0
+        while True:
+            t += rng.exponential(1.0 / rate)
+            if t >= duration_s:
+                break
+            out.append(Request(det=d, ring_index=n % k, t_arrival=t))
+            n += 1
+    return sorted(out, key=lambda r: r.t_arrival)

@@ -20,6 +20,7 @@ from .scene import (  # noqa: F401
     JUNGFRAU4M,
     JUNGFRAU1M,
     JUNGFRAU16M,
+    JUNGFRAU9M,
     GEOMETRIES,
     stripe_mask,
     scattering_angle_deg,

@@ -101,7 +101,14 @@ JUNGFRAU16M = Geometry(
     mask_rows=((1028, 1056), (3108, 3136)), mask_cols=((1030, 1058), (3300, 3328)),
 )
 
-GEOMETRIES = {g.name: g for g in (SMALL, JUNGFRAU4M, JUNGFRAU1M, JUNGFRAU16M)}
+JUNGFRAU9M = Geometry(
+    name="jungfrau-9m", config_id=4, height=3114, width=3132, pixel_m=75e-6,
+    dist_m=0.1, centre_row=1557.3, centre_col=1566.7, wavelength_m=1e-10,
+    n_bins=1500, split="bbox", normalised=True, raw=True, spots=(0, 200),
+    mask_rows=((1038, 1064), (2076, 2102)), mask_cols=((1044, 1070), (2088, 2114)),
+)
+
+GEOMETRIES = {g.name: g for g in (SMALL, JUNGFRAU4M, JUNGFRAU1M, JUNGFRAU16M, JUNGFRAU9M)}
 
 
 def _rng(geom: Geometry, stream: int) -> np.random.Generator:
