@@ -22,12 +22,17 @@ to diffraction image compression and serial crystallography", 2024):
   poisson, varianceP, sem), iterative sigma-clipping (eq. clip, Sec. 2.4) and
   the Chauvenet cut-off (eq. chauvenet);
 * ``classify``  -- per-pixel background lookup, sparsification (Sec. 3),
-  densification, and the peak finder (Sec. 4).
+  densification, noise free and with regenerated noise (Sec. 3.2), the peak
+  finder and the peak-count veto (Sec. 4);
+* ``rng``       -- the counter-based generator (Philox4x32-10) and the
+  Box-Muller normals of the noisy densification, pinned by the generator's
+  published known-answer vectors.
 
 Readings where the paper is silent are stated in each function's docstring.
 Parity unpinned by the paper (pinned only by stated definitions): the raw-word
 correction, the bounding-box splitting rule, the per-pixel background
-interpolation and the peak-record definition.
+interpolation, the peak-record definition, and the noise convention of the
+noisy densification (generator, truncation).
 """
 
-from . import geometry, correct, stats, classify  # noqa: F401
+from . import geometry, correct, stats, classify, rng  # noqa: F401

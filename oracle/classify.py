@@ -80,6 +80,52 @@ def densify(indices, values, n_pix, mask, position, centres, profile, valid=None
     return dense
 
 
+def densify_noisy(indices, values, n_pix, mask, position, centres, profile, seed, frame, trunc=np.inf):
+    """Dense frame with regenerated background noise (float64 [n_pix]).
+
+    Sec. 3.2 asks for the background to be rebuilt "with noise" of the
+    original's spread for programs that analyse noise.  Reading: a pixel
+    that was not kept gets mu_i + sigma_i z_i, z_i a standard normal of the
+    counter-based generator of ``oracle.rng`` (seed, absolute frame number,
+    pixel), drawn at most ``trunc``: a pixel that was not kept lay at most
+    n_pick sigma above the background, so passing trunc = n_pick keeps the
+    regenerated noise below the sparsification threshold (the first of the
+    pixel's two normals not above trunc, else trunc itself).  Kept pixels get
+    their stored value, masked pixels 0.
+    """
+    from . import rng
+    mu, sd = background_at(position, centres, profile)
+    za, zb = rng.pixel_normals(seed, frame, n_pix)
+    z = rng.truncated(za, zb, trunc)
+    ok = np.ones(n_pix, dtype=bool) if mask is None else np.asarray(mask).reshape(-1) == 0
+    dense = np.where(ok, mu + sd * z, 0.0)
+    dense[np.asarray(indices)] = values
+    return dense
+
+
+def veto(n_peaks, n_kept, threshold, hist_bins=256):
+    """Peak-count veto of Sec. 4 ("Peak count as veto algorithm").
+
+    A frame is a hit when its peak count reaches the threshold; the
+    acquisition keeps hits and may discard the rest.  Besides the per-frame
+    decision the counters needed to choose the threshold live are returned:
+    hits, non-hits, kept entries (the sparse payload) of each, and for every
+    peak count p < hist_bins - 1 the number of frames and of kept entries
+    with exactly p peaks (the last bin collects p >= hist_bins - 1).  For any
+    threshold T < hist_bins the frames (payload) a veto at T would discard
+    are the sums of those histograms below T.
+    """
+    n_peaks = np.asarray(n_peaks, dtype=np.int64)
+    n_kept = np.asarray(n_kept, dtype=np.int64)
+    hit = n_peaks >= threshold
+    b = np.minimum(n_peaks, hist_bins - 1)
+    return dict(hit=hit,
+                hits=int(hit.sum()), misses=int((~hit).sum()),
+                kept_hits=int(n_kept[hit].sum()), kept_misses=int(n_kept[~hit].sum()),
+                hist_frames=np.bincount(b, minlength=hist_bins).astype(np.int64),
+                hist_kept=np.bincount(b, weights=n_kept, minlength=hist_bins).astype(np.int64))
+
+
 def _shift(a, dy, dx, fill):
     """out[y, x] = a[y + dy, x + dx] where in bounds, else ``fill``."""
     H, W = a.shape
