@@ -262,6 +262,39 @@ def surrogate_vs_plain(api, torch, geo, pipe, train_raw, frames, steps, reps=5):
     }
 
 
+def densify_and_veto(api, torch, geo, pipe, n_frames, reps=10):
+    """Decompression of the step's own sparse output (Sec. 3.2): noise free and
+    with regenerated noise, plus the peak-count veto over its peak counts."""
+    stream = torch.cuda.current_stream()
+    sparse = {k: pipe.out[k] for k in ("kept_index", "kept_value", "n_kept")}
+    prof = pipe.profile
+    out = torch.empty((n_frames, geo.n_pix), dtype=torch.float32, device=pipe.frames.device)
+    ws = torch.empty(int(api.B.lib().ss_densify_workspace(n_frames, geo.n_bins)), dtype=torch.uint8,
+                     device=out.device)
+    n_kept = int(torch.clamp(pipe.out["n_kept"], max=pipe.kept_capacity).sum())
+    # dense frames written once, radial codes read once per 8 frames, kept entries read and written
+    alg = 4 * geo.n_pix * n_frames + 4 * geo.n_pix * ((n_frames + 7) // 8) + 12 * n_kept
+    res = {"frames": n_frames, "algorithmic_bytes": alg}
+    for name, noise in (("noise_free", None), ("noisy", dict(seed=2024, frame0=0, trunc=3.0))):
+        api.densify(sparse, geo, prof, noise=noise, out=out, workspace=ws)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        torch.cuda.synchronize()
+        ev[0].record(stream)
+        for _ in range(reps):
+            api.densify(sparse, geo, prof, noise=noise, out=out, workspace=ws)
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        ms = ev[0].elapsed_time(ev[1]) / reps
+        res[name] = {"ms": round(ms, 4), "frames_per_s": round(n_frames / (ms * 1e-3), 1),
+                     "achieved_gbs": round(alg / (ms * 1e-3) / 1e9, 1)}
+    counters = api.new_veto_counters(out.device)
+    hit, counters = api.veto(pipe.out["n_peaks"], 20, pipe.out["n_kept"], counters)
+    v = api.veto_summary(counters)
+    res["veto_threshold_20"] = {"hits": v["hits"], "misses": v["misses"],
+                                "kept_entries_discarded": v["kept_misses"]}
+    return res
+
+
 def cpu_baseline(raw, budget_s=20.0):
     """The FP64 oracle, as it stands, on the first frames of the batch."""
     from oracle import classify as OK
@@ -349,6 +382,7 @@ def main():
     ap.add_argument("--train-steps", type=int, default=3000)
     ap.add_argument("--no-batched", action="store_true", help="skip the mixed-detector batch")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
+    ap.add_argument("--no-densify", action="store_true", help="skip the densification timing")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 1 GiB device copy (a known-size reference for HBM counters)")
     args = ap.parse_args()
@@ -448,6 +482,11 @@ def main():
         sur = surrogate_vs_plain(api, torch, geo, pipe, train_np, frames_bench, args.train_steps)
         print(f"# surrogate: {sur}", file=sys.stderr, flush=True)
 
+    dense = None
+    if not args.no_densify:
+        dense = densify_and_veto(api, torch, geo, pipe, F)
+        print(f"# densify: {dense}", file=sys.stderr, flush=True)
+
     cache = {"jungfrau-4m": (geo, pipe.pedestal, pipe.gain)}
     batched = None
     if uneven_np is not None:
@@ -501,6 +540,7 @@ def main():
         "surrogate_vs_plain": sur,
         "batched_uneven": batched,
         "serving": served,
+        "densify": dense,
         "cpu_baseline": cpu,
         "paper_context": "about 4 ms/frame (250 frames/s) on one V100 + one POWER9 core; 925 Hz-1 kHz "
                          "production on 2 hosts x 2 V100 (other hardware, not a target)",

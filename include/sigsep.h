@@ -333,6 +333,76 @@ int ss_peakfind(const float *frames, const uint8_t *mask, int32_t n_frames,
                 void *workspace, size_t workspace_bytes, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
+ * Densification (Sec. 3.2) and the peak-count veto (Sec. 4).
+ */
+
+/*
+ * Noise of a densified background.  The paper regenerates the background
+ * "with noise" for analysis programs that measure noise (Sec. 3.2) and fixes
+ * no generator; this library's convention: pixel i of absolute frame
+ * frame0 + f takes generator block i / 2 of Philox4x32-10 (Salmon et al.,
+ * SC 2011) with counter (i / 2, frame0 + f, 0, 0) and key (seed & 0xffffffff,
+ * seed >> 32); the even pixel of a block uses words 0, 1, the odd one words
+ * 2, 3, as u1 = ((w >> 8) + 1) 2^-24 and u2 = (w >> 8) 2^-24; Box-Muller gives
+ * z_a = r cos(2 pi u2), z_b = r sin(2 pi u2), r = sqrt(-2 ln u1); the pixel's
+ * draw is the first of z_a, z_b not above trunc, else trunc (pass INFINITY
+ * for no bound; n_pick keeps regenerated noise under the sparsification
+ * threshold).  Computed in float32; the background in float64.
+ */
+typedef struct {
+    uint64_t seed;
+    int64_t frame0;
+    float trunc;
+} ss_noise;
+
+/* Workspace (device bytes) of ss_densify for n_frames frames and n_bins bins. */
+size_t ss_densify_workspace(int32_t n_frames, int32_t n_bins);
+
+/*
+ * ss_densify -- dense frames from their sparse representation (Sec. 3.2):
+ * the inverse of ss_compress.  Every pixel gets the background mu_i of its
+ * frame's profile (interpolated between the centres of the non-empty bins
+ * as in ss_classify), plus sigma_i z_i when noise != NULL; masked pixels
+ * (mask[i] != 0 or SS_RC_MASKED) get 0; then entries k < min(n_kept[f],
+ * capacity) of frame f put kept_value back at kept_index (indices >= n_pix
+ * are skipped).
+ *   kept_index, kept_value [dev] [n_frames][capacity] (ss_compress layout),
+ *     n_kept [dev] int64 [n_frames]; all three may be NULL when capacity = 0
+ *   mask [dev] uint8 [n_pix] or NULL; radial, profile: [host] structs with
+ *     [dev] arrays (profile mean, std, n_members used)
+ *   noise [host] or NULL (noise free)
+ *   dense [dev] float [n_frames][n_pix], written entirely
+ *   workspace [dev] >= ss_densify_workspace(n_frames, radial->n_bins) bytes
+ * Errors: SS_EINVAL (null pointers, NaN trunc), SS_ESIZE (sizes,
+ * workspace), SS_EHIP.
+ */
+int ss_densify(const uint32_t *kept_index, const float *kept_value, int64_t capacity,
+               const int64_t *n_kept, const uint8_t *mask, int32_t n_frames, int64_t n_pix,
+               const ss_radial *radial, const ss_profile *profile, const ss_noise *noise,
+               float *dense, void *workspace, size_t workspace_bytes, hipStream_t stream);
+
+#define SS_VETO_BINS 256
+#define SS_VETO_COUNTERS (4 + 2 * SS_VETO_BINS)
+
+/*
+ * ss_veto -- the peak-count veto of Sec. 4: frame f is a hit when
+ * n_peaks[f] >= threshold (the acquisition may discard the others), and the
+ * counters from which a live threshold is chosen.  counters [dev] int64
+ * [SS_VETO_COUNTERS] are ADDED to (zero them once; they accumulate over
+ * calls): [0] hits, [1] non-hits, [2] kept entries of hits, [3] kept entries
+ * of non-hits, [4 + p] frames with p peaks, [4 + SS_VETO_BINS + p] their kept
+ * entries (p clamped to 0 .. SS_VETO_BINS - 1).  For any threshold
+ * T < SS_VETO_BINS, the frames and kept entries a veto at T discards are the
+ * sums of the two histograms below T.
+ *   n_peaks [dev] int64 [n_frames]; n_kept [dev] int64 [n_frames] or NULL
+ *   (counted as 0); hit [dev] uint8 [n_frames] or NULL.
+ * Calls that overlap on one counters array add concurrently (atomically).
+ * Errors: SS_EINVAL, SS_ESIZE (n_frames < 0), SS_EHIP.
+ */
+int ss_veto(const int64_t *n_peaks, const int64_t *n_kept, int32_t n_frames, int64_t threshold,
+            uint8_t *hit, int64_t *counters, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
  * Learned clip surrogate.  Not in the paper: the paper's clip time grows
  * with the number of passes (Sec. 2.4); a small network predicts each bin's
  * converged clipped mean and std from the bin's unclipped statistics and a

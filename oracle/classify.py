@@ -111,14 +111,15 @@ def veto(n_peaks, n_kept, threshold, hist_bins=256):
     decision the counters needed to choose the threshold live are returned:
     hits, non-hits, kept entries (the sparse payload) of each, and for every
     peak count p < hist_bins - 1 the number of frames and of kept entries
-    with exactly p peaks (the last bin collects p >= hist_bins - 1).  For any
+    with exactly p peaks (the last bin collects p >= hist_bins - 1, the first
+    any count below 0, which the path never produces).  For any
     threshold T < hist_bins the frames (payload) a veto at T would discard
     are the sums of those histograms below T.
     """
     n_peaks = np.asarray(n_peaks, dtype=np.int64)
     n_kept = np.asarray(n_kept, dtype=np.int64)
     hit = n_peaks >= threshold
-    b = np.minimum(n_peaks, hist_bins - 1)
+    b = np.clip(n_peaks, 0, hist_bins - 1)
     return dict(hit=hit,
                 hits=int(hit.sum()), misses=int((~hit).sum()),
                 kept_hits=int(n_kept[hit].sum()), kept_misses=int(n_kept[~hit].sum()),

@@ -164,8 +164,8 @@ def new_profile(n_frames, n_bins, device="cuda"):
 
 
 def profile_c(prof) -> B.Profile:
-    return B.Profile(*(prof[k].data_ptr() for k in ("mean", "std", "sem", "sum_w", "n_members", "n_iter",
-                                                    "converged")))
+    return B.Profile(*(prof[k].data_ptr() if prof.get(k) is not None else None
+                       for k in ("mean", "std", "sem", "sum_w", "n_members", "n_iter", "converged")))
 
 
 def sigma_clip(frames, geom: Geometry, params: Params, out=None, norm=None, mask=None, integrate_only=False):
@@ -418,6 +418,64 @@ def peakfind(frames, geom, profile, params, peak_capacity, mask=None, workspace=
         ctypes.byref(profile_c(profile)), ctypes.byref(params.c()), _p(out["peaks"]), peak_capacity,
         _p(out["n_peaks"]), _p(workspace), workspace.numel(), _stream()))
     return out
+
+
+def densify(sparse, geom: Geometry, profile, n_frames=None, noise=None, mask=None, out=None, workspace=None):
+    """Dense frames [F, N] float32 from kept pixels and their profile (Sec. 3.2).
+
+    ``sparse``: dict with kept_index [F, cap] int32, kept_value [F, cap]
+    float32 and n_kept [F] int64 (the layout ``compress`` returns), or None
+    for background only (then give ``n_frames``).  ``profile``: dict with
+    mean, std [F, nb] float64 and n_members [F, nb] int32.  ``noise``: None
+    (noise free) or dict(seed=int, frame0=int, trunc=float) -- the draw
+    convention is that of ``ss_densify``.
+    """
+    ref = profile["mean"]
+    F = int(n_frames if sparse is None else sparse["n_kept"].shape[0])
+    dev = ref.device
+    _need_device(mask, out, workspace, ref, profile["std"], profile["n_members"],
+                 *(() if sparse is None else (sparse["kept_index"], sparse["kept_value"], sparse["n_kept"])))
+    if out is None:
+        out = torch.empty((F, geom.n_pix), dtype=torch.float32, device=dev)
+    if workspace is None:
+        workspace = torch.empty(int(B.lib().ss_densify_workspace(F, geom.n_bins)), dtype=torch.uint8, device=dev)
+    cap = 0 if sparse is None else sparse["kept_index"].shape[1]
+    nz = None
+    if noise is not None:
+        nz = B.Noise(int(noise.get("seed", 0)) & ((1 << 64) - 1), int(noise.get("frame0", 0)),
+                     float(noise.get("trunc", float("inf"))))
+    B.check("ss_densify", B.lib().ss_densify(
+        _p(None if sparse is None else sparse["kept_index"]), _p(None if sparse is None else sparse["kept_value"]),
+        cap, _p(None if sparse is None else sparse["n_kept"]), _p(mask), F, geom.n_pix,
+        ctypes.byref(geom.radial()), ctypes.byref(profile_c(profile)),
+        None if nz is None else ctypes.byref(nz), _p(out), _p(workspace), workspace.numel(), _stream()))
+    return out
+
+
+def new_veto_counters(device="cuda"):
+    """Zeroed counters for ``veto`` (they accumulate over calls)."""
+    return torch.zeros(B.SS_VETO_COUNTERS, dtype=torch.int64, device=device)
+
+
+def veto(n_peaks, threshold, n_kept=None, counters=None, hit=None):
+    """Peak-count veto (Sec. 4): hit [F] uint8 and the accumulated counters."""
+    _need_device(n_peaks, n_kept, counters, hit)
+    F = n_peaks.numel()
+    if counters is None:
+        counters = new_veto_counters(n_peaks.device)
+    if hit is None:
+        hit = torch.empty(F, dtype=torch.uint8, device=n_peaks.device)
+    B.check("ss_veto", B.lib().ss_veto(_p(n_peaks), _p(n_kept), F, int(threshold), _p(hit), _p(counters),
+                                       _stream()))
+    return hit, counters
+
+
+def veto_summary(counters):
+    """Host view of the veto counters."""
+    c = counters.cpu().numpy()
+    nb = B.SS_VETO_BINS
+    return dict(hits=int(c[0]), misses=int(c[1]), kept_hits=int(c[2]), kept_misses=int(c[3]),
+                hist_frames=c[4:4 + nb].copy(), hist_kept=c[4 + nb:4 + 2 * nb].copy())
 
 
 def peaks_to_numpy(peaks_u8, n):

@@ -29,6 +29,8 @@ SS_MLP_K1, SS_MLP_OUT_PAD = 32, 16
 SS_MLP_OFF_W1, SS_MLP_OFF_B1, SS_MLP_OFF_W2 = 0, 2048, 2112
 SS_MLP_OFF_B2, SS_MLP_OFF_W3, SS_MLP_OFF_B3 = 6208, 6272, 7296
 SS_MLP_PARAMS = 7312
+SS_VETO_BINS = 256
+SS_VETO_COUNTERS = 4 + 2 * SS_VETO_BINS
 
 EXPORTED = (
     "ss_strerror", "ss_version", "ss_build_csr", "ss_csr_schedule", "ss_class_rows", "ss_radial_coords",
@@ -37,6 +39,7 @@ EXPORTED = (
     "ss_compress", "ss_peakfind",
     "ss_clip_features", "ss_surrogate_targets", "ss_mlp_forward", "ss_mlp_grad_workspace", "ss_mlp_grad",
     "ss_mlp_adam", "ss_sigma_clip_surrogate", "ss_sigma_clip_batches",
+    "ss_densify_workspace", "ss_densify", "ss_veto",
 )
 
 
@@ -78,6 +81,10 @@ class Radial(ctypes.Structure):
 class Peak(ctypes.Structure):
     _fields_ = [("index", ctypes.c_uint32), ("y", ctypes.c_float), ("x", ctypes.c_float),
                 ("intensity", ctypes.c_float), ("sigma", ctypes.c_float)]
+
+
+class Noise(ctypes.Structure):
+    _fields_ = [("seed", ctypes.c_uint64), ("frame0", ctypes.c_int64), ("trunc", ctypes.c_float)]
 
 
 PEAK_BYTES = ctypes.sizeof(Peak)
@@ -141,6 +148,12 @@ def lib():
         L.ss_sigma_clip_surrogate.argtypes = [vp, vp, vp, i32, P(Csr), P(Params), vp, f32, P(Profile), vp, vp]
         L.ss_sigma_clip_batches.restype = ctypes.c_int
         L.ss_sigma_clip_batches.argtypes = [vp, i32, P(Params), vp]
+        L.ss_densify_workspace.restype = sz
+        L.ss_densify_workspace.argtypes = [i32, i32]
+        L.ss_densify.restype = ctypes.c_int
+        L.ss_densify.argtypes = [vp, vp, i64, vp, vp, i32, i64, P(Radial), P(Profile), P(Noise), vp, vp, sz, vp]
+        L.ss_veto.restype = ctypes.c_int
+        L.ss_veto.argtypes = [vp, vp, i32, i64, vp, vp, vp]
         _lib = L
     return _lib
 

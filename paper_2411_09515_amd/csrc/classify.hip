@@ -17,6 +17,12 @@
 // per frame turns the counts into exclusive offsets (k_tile_scan), and the
 // tiles write their entries in pixel order at those offsets (k_tile_write),
 // computing peak records on the way.
+//
+// The inverse direction (Sec. 3.2): k_densify rebuilds dense frames from the
+// same background table -- noise free, or with noise drawn from a
+// counter-based generator -- and k_densify_scatter puts the kept pixels
+// back.  k_veto turns per-frame peak counts into the hit decision of Sec. 4
+// and accumulates the counters a live veto threshold is chosen from.
 
 #include <cmath>
 
@@ -617,6 +623,157 @@ void launch_compaction(const ClassArgs &a, hipStream_t stream) {
     k_tile_write<KEEP, PEAKS><<<grid, kBlock, 0, stream>>>(a);
 }
 
+
+// ---- densification (Sec. 3.2) -----------------------------------------------------------
+
+constexpr int kDenseBlock = 256;
+constexpr int kDensePPT = 4;     // consecutive pixels per thread (two generator blocks, one 16-byte store)
+constexpr int kDenseFrames = 8;  // frames per work-group: radial codes read once per 8 frames
+constexpr int kScatterBlock = 256;
+constexpr int kVetoBlock = 256;
+
+struct DenseArgs {
+    const uint32_t *rcoord;
+    const uint8_t *mask;
+    int64_t n_pix;
+    int32_t n_frames;
+    int32_t n_bins;
+    const Seg *table;
+    float *dense;
+    int32_t noisy;
+    uint32_t key0, key1;
+    int64_t frame0;
+    float trunc;
+    int32_t vec_ok;  // n_pix % 4 == 0 and dense 16-byte aligned: 16-byte stores
+};
+
+// Philox4x32-10 (Salmon et al., SC 2011) on the counter c under key (k0, k1):
+// ten rounds of two 32 x 32 -> 64-bit products whose high halves are mixed
+// into the other two words with the round key; the key advances by the two
+// Weyl constants after every round.
+__device__ inline void philox4x32_10(uint32_t (&c)[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c[0]), lo0 = 0xD2511F53u * c[0];
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c[2]), lo1 = 0xCD9E8D57u * c[2];
+        const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = lo1;
+        c[2] = n2;
+        c[3] = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+}
+
+// A pixel's standard normal from two generator words: Box-Muller on the
+// 24-bit uniforms u1 in (0, 1] and u2 in [0, 1) (exact in float32), the
+// first of the pair's two normals not above trunc, else trunc.
+__device__ inline float noise_draw(uint32_t w1, uint32_t w2, float trunc) {
+    const float u1 = float((w1 >> 8) + 1u) * 0x1p-24f;
+    const float u2 = float(w2 >> 8) * 0x1p-24f;
+    const float r = sqrtf(-2.0f * logf(u1));
+    float sn, cs;
+    sincospif(2.0f * u2, &sn, &cs);
+    const float za = r * cs, zb = r * sn;
+    return za <= trunc ? za : (zb <= trunc ? zb : trunc);
+}
+
+// One thread owns kDensePPT consecutive pixels for up to kDenseFrames
+// frames: background mu (and sigma) from the frame's table in float64,
+// plus sigma z for the noisy variant, 0 for masked pixels.  Pixel i draws
+// from generator block i / 2 of counter (i / 2, absolute frame, 0, 0); the
+// even pixel of a block takes words 0 and 1, the odd one words 2 and 3.
+__global__ __launch_bounds__(kDenseBlock) void k_densify(DenseArgs a) {
+    const int64_t p0 = (int64_t(blockIdx.x) * kDenseBlock + threadIdx.x) * kDensePPT;
+    if (p0 >= a.n_pix) return;
+    const int np = int(min(int64_t(kDensePPT), a.n_pix - p0));
+    const int f0 = int(blockIdx.y) * kDenseFrames;
+    const int f1 = min(a.n_frames, f0 + kDenseFrames);
+    uint32_t rc[kDensePPT];
+#pragma unroll
+    for (int k = 0; k < kDensePPT; ++k) {
+        rc[k] = SS_RC_MASKED;
+        if (k < np) {
+            rc[k] = a.rcoord[p0 + k];
+            if (a.mask && a.mask[p0 + k]) rc[k] = SS_RC_MASKED;
+        }
+    }
+    const bool vec = np == kDensePPT && a.vec_ok;
+    for (int f = f0; f < f1; ++f) {
+        const Seg *__restrict__ tab = a.table + int64_t(f) * (a.n_bins + 1);
+        uint32_t w[2 * kDensePPT];
+        if (a.noisy) {
+            const uint32_t fr = uint32_t(a.frame0 + f);
+#pragma unroll
+            for (int b = 0; b < kDensePPT / 2; ++b) {
+                uint32_t c[4] = {uint32_t(p0 >> 1) + uint32_t(b), fr, 0u, 0u};
+                philox4x32_10(c, a.key0, a.key1);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) w[4 * b + j] = c[j];
+            }
+        }
+        float out[kDensePPT];
+#pragma unroll
+        for (int k = 0; k < kDensePPT; ++k) {
+            out[k] = 0.0f;
+            if (rc[k] != SS_RC_MASKED) {
+                double mu, sd;
+                background(rc[k], tab, a.n_bins, 0.0, mu, sd);
+                out[k] = a.noisy ? float(mu + sd * double(noise_draw(w[2 * k], w[2 * k + 1], a.trunc))) : float(mu);
+            }
+        }
+        float *dst = a.dense + int64_t(f) * a.n_pix + p0;
+        if (vec) {
+            *reinterpret_cast<float4 *>(dst) = make_float4(out[0], out[1], out[2], out[3]);
+        } else {
+#pragma unroll
+            for (int k = 0; k < kDensePPT; ++k)
+                if (k < np) dst[k] = out[k];
+        }
+    }
+}
+
+// Kept pixels back into their frames: entry k < min(n_kept, capacity) of
+// frame f writes its value at its index; indices past the frame are skipped.
+__global__ __launch_bounds__(kScatterBlock) void k_densify_scatter(const uint32_t *__restrict__ idx,
+                                                                   const float *__restrict__ val, int64_t capacity,
+                                                                   const int64_t *__restrict__ n_kept, int64_t n_pix,
+                                                                   float *__restrict__ dense) {
+    const int f = blockIdx.y;
+    const int64_t n = min(max(n_kept[f], int64_t(0)), capacity);
+    const int64_t o = int64_t(f) * capacity;
+    for (int64_t k = int64_t(blockIdx.x) * kScatterBlock + threadIdx.x; k < n;
+         k += int64_t(gridDim.x) * kScatterBlock) {
+        const uint32_t i = idx[o + k];
+        if (int64_t(i) < n_pix) dense[int64_t(f) * n_pix + i] = val[o + k];
+    }
+}
+
+// ---- peak-count veto (Sec. 4) -----------------------------------------------------------
+
+// Frame f is a hit when n_peaks[f] >= threshold.  Counters (int64, added to,
+// so they accumulate over calls): [0] hits, [1] non-hits, [2] kept entries of
+// hits, [3] kept entries of non-hits, [4 + p] frames with p peaks and
+// [4 + SS_VETO_BINS + p] their kept entries, p clamped to [0, SS_VETO_BINS - 1].
+// Integer sums: the totals do not depend on the order of the additions.
+__global__ __launch_bounds__(kVetoBlock) void k_veto(const int64_t *__restrict__ n_peaks,
+                                                     const int64_t *__restrict__ n_kept, int32_t n_frames,
+                                                     int64_t threshold, uint8_t *__restrict__ hit,
+                                                     unsigned long long *__restrict__ counters) {
+    const int f = int(blockIdx.x) * kVetoBlock + int(threadIdx.x);
+    if (f >= n_frames) return;
+    const int64_t p = n_peaks[f];
+    const unsigned long long k = n_kept ? (unsigned long long)max(n_kept[f], int64_t(0)) : 0ull;
+    const bool h = p >= threshold;
+    if (hit) hit[f] = h ? 1 : 0;
+    const int b = int(min(max(p, int64_t(0)), int64_t(SS_VETO_BINS - 1)));
+    atomicAdd(counters + (h ? 0 : 1), 1ull);
+    atomicAdd(counters + (h ? 2 : 3), k);
+    atomicAdd(counters + 4 + b, 1ull);
+    atomicAdd(counters + 4 + SS_VETO_BINS + b, k);
+}
+
 }  // namespace
 }  // namespace ss
 
@@ -731,4 +888,76 @@ extern "C" int ss_peakfind(const float *frames, const uint8_t *mask, int32_t n_f
     if (!peaks || !n_peaks) return SS_EINVAL;
     return ss_classify(frames, mask, n_frames, height, width, radial, profile, params, nullptr, nullptr, 0,
                        nullptr, peaks, peak_capacity, n_peaks, workspace, ws_bytes, stream);
+}
+
+extern "C" size_t ss_densify_workspace(int32_t n_frames, int32_t n_bins) {
+    if (n_frames < 0 || n_bins < 0) return 0;
+    using namespace ss;
+    return 256 + align256(size_t(n_frames) * size_t(n_bins + 1) * sizeof(SegF)) +
+           align256(size_t(n_frames) * size_t(n_bins + 1) * sizeof(Seg));
+}
+
+extern "C" int ss_densify(const uint32_t *kept_index, const float *kept_value, int64_t capacity,
+                          const int64_t *n_kept, const uint8_t *mask, int32_t n_frames, int64_t n_pix,
+                          const ss_radial *radial, const ss_profile *profile, const ss_noise *noise, float *dense,
+                          void *workspace, size_t ws_bytes, hipStream_t stream) {
+    using namespace ss;
+    if (!radial || !profile) return SS_EINVAL;
+    if (n_frames < 0 || n_pix < 0 || capacity < 0) return SS_ESIZE;
+    if (n_pix >= (int64_t(1) << 31) || n_frames > 65535) return SS_ESIZE;
+    if (radial->n_bins <= 0 || radial->n_bins > SS_MAX_BINS) return SS_ESIZE;
+    if (noise && !(noise->trunc == noise->trunc)) return SS_EINVAL;  // NaN truncation
+    if (n_frames == 0 || n_pix == 0) return SS_OK;
+    if (!dense || !radial->rcoord || !profile->mean || !profile->std || !profile->n_members || !workspace)
+        return SS_EINVAL;
+    if (capacity > 0 && (!kept_index || !kept_value || !n_kept)) return SS_EINVAL;
+    if (ws_bytes < ss_densify_workspace(n_frames, radial->n_bins)) return SS_ESIZE;
+
+    Workspace ws{};
+    uintptr_t q = (reinterpret_cast<uintptr_t>(workspace) + 255) & ~uintptr_t(255);
+    ws.tablef = reinterpret_cast<SegF *>(q);
+    q += align256(size_t(n_frames) * size_t(radial->n_bins + 1) * sizeof(SegF));
+    ws.table = reinterpret_cast<Seg *>(q);
+    k_profile_table<<<dim3(uint32_t(n_frames)), kTableBlock, 0, stream>>>(
+        profile->mean, profile->std, profile->n_members, radial->n_bins, ws, 0, nullptr, nullptr);
+    SS_RETURN_IF_LAUNCH_FAILED();
+
+    DenseArgs a;
+    a.rcoord = radial->rcoord;
+    a.mask = mask;
+    a.n_pix = n_pix;
+    a.n_frames = n_frames;
+    a.n_bins = radial->n_bins;
+    a.table = ws.table;
+    a.dense = dense;
+    a.noisy = noise ? 1 : 0;
+    a.key0 = noise ? uint32_t(noise->seed & 0xFFFFFFFFu) : 0u;
+    a.key1 = noise ? uint32_t(noise->seed >> 32) : 0u;
+    a.frame0 = noise ? noise->frame0 : 0;
+    a.trunc = noise ? noise->trunc : 0.0f;
+    a.vec_ok = (n_pix % kDensePPT) == 0 && (reinterpret_cast<uintptr_t>(dense) % 16) == 0;
+    const int64_t threads = (n_pix + kDensePPT - 1) / kDensePPT;
+    const dim3 grid(uint32_t((threads + kDenseBlock - 1) / kDenseBlock),
+                    uint32_t((n_frames + kDenseFrames - 1) / kDenseFrames));
+    k_densify<<<grid, kDenseBlock, 0, stream>>>(a);
+    SS_RETURN_IF_LAUNCH_FAILED();
+    if (capacity > 0) {
+        const int64_t blocks = min(int64_t(256), (capacity + kScatterBlock - 1) / kScatterBlock);
+        k_densify_scatter<<<dim3(uint32_t(blocks), uint32_t(n_frames)), kScatterBlock, 0, stream>>>(
+            kept_index, kept_value, capacity, n_kept, n_pix, dense);
+        SS_RETURN_IF_LAUNCH_FAILED();
+    }
+    return SS_OK;
+}
+
+extern "C" int ss_veto(const int64_t *n_peaks, const int64_t *n_kept, int32_t n_frames, int64_t threshold,
+                       uint8_t *hit, int64_t *counters, hipStream_t stream) {
+    using namespace ss;
+    if (n_frames < 0) return SS_ESIZE;
+    if (n_frames == 0) return SS_OK;
+    if (!n_peaks || !counters) return SS_EINVAL;
+    k_veto<<<dim3(uint32_t((n_frames + kVetoBlock - 1) / kVetoBlock)), kVetoBlock, 0, stream>>>(
+        n_peaks, n_kept, n_frames, threshold, hit, reinterpret_cast<unsigned long long *>(counters));
+    SS_RETURN_IF_LAUNCH_FAILED();
+    return SS_OK;
 }

@@ -10,7 +10,9 @@ words, no statistics, no clipping, no classification.
 Every draw comes from ``numpy.random.default_rng`` seeded with a
 ``SeedSequence([config_id, frame_idx])`` (calibration: ``[config_id, 999999]``;
 the clip surrogate's training frames: ``[config_id, 1000000 + frame_idx]``;
-the batched mixed-detector frames: ``[config_id, 2000000 + frame_idx]``),
+the batched mixed-detector frames: ``[config_id, 2000000 + frame_idx]``;
+the stored sparse frames read by densification:
+``[config_id, 3000000 + frame_idx]``),
 so both sides see identical bytes.
 """
 
@@ -35,4 +37,5 @@ from .scene import (  # noqa: F401
     jungfrau_frames,
     training_frame,
     uneven_frame,
+    stored_sparse,
 )

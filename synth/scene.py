@@ -278,6 +278,30 @@ def uneven_frame(geom: Geometry, frame_idx: int, hit_rate: float = 0.3, max_spot
     return _encode(geom, rng, photons, truth)
 
 
+def stored_sparse(geom: Geometry, frame_idx: int, kept_fraction: float = 0.02, empty_fraction: float = 0.05):
+    """A stored sparse frame as densification reads it: a background profile
+    (mean, std, member count per radial bin; about ``empty_fraction`` of the
+    bins empty) and kept pixels (ascending unmasked indices, about
+    ``kept_fraction`` of the pixels, with intensities well above the
+    background).  Shapes only: the profile is a smooth decreasing curve with
+    jitter, not the result of any statistics over a frame.
+    Stream: ``[config_id, 3000000 + frame_idx]``.
+    """
+    rng = _rng(geom, 3_000_000 + frame_idx)
+    nb = geom.n_bins
+    r = np.arange(nb, dtype=np.float64) / nb
+    mean = (40.0 * np.exp(-3.0 * r) + 2.0) * rng.uniform(0.97, 1.03, nb)
+    std = np.sqrt(mean) * rng.uniform(0.8, 1.2, nb)
+    members = rng.integers(20, 5000, nb).astype(np.int32)
+    members[rng.random(nb) < empty_fraction] = 0
+    members[:2] = 0  # the innermost bins (behind the beam stop) are empty
+    ok = np.nonzero(stripe_mask(geom).reshape(-1) == 0)[0]
+    n = int(round(kept_fraction * ok.size))
+    idx = np.sort(rng.choice(ok, n, replace=False)).astype(np.int64)
+    val = (mean.max() + rng.exponential(50.0, n)).astype(np.float32)
+    return dict(mean=mean, std=std, n_members=members, kept_index=idx, kept_value=val)
+
+
 def _encode(geom: Geometry, rng: np.random.Generator, photons: np.ndarray, truth):
     ped, gain = jungfrau_calibration(geom)
     e = photons.reshape(-1)
