@@ -309,7 +309,7 @@ size_t ss_classify_workspace(int32_t n_frames, int64_t n_pix, int32_t n_bins);
  *   radial, profile, params: [host] structs with [dev] arrays
  *   workspace [dev] >= ss_classify_workspace(...) bytes
  * Errors: SS_EINVAL, SS_ESIZE (workspace too small, capacities < 0,
- * bin count mismatch), SS_EHIP.
+ * bin count mismatch, height * width >= 2^29), SS_EHIP.
  */
 int ss_classify(const float *frames, const uint8_t *mask, int32_t n_frames,
                 int32_t height, int32_t width, const ss_radial *radial,

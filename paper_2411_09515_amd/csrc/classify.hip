@@ -44,10 +44,11 @@ struct Seg {
     int32_t lo, pad;
 };
 
-// The same interpolation segment in float32 for the fast path.
-struct SegF {
-    float m_lo, dm, s_lo, ds, inv_span;
-    int32_t lo;
+// The same interpolation in float32 for the fast path, as a line in the
+// pixel's fraction of its interval: mu = a + b frac, sigma = c + d frac
+// (a, b, c, d computed in float64 per interval and rounded once).
+struct alignas(16) SegF {
+    float a, b, c, d;
 };
 
 struct Workspace {
@@ -159,8 +160,11 @@ __global__ __launch_bounds__(kTableBlock) void k_profile_table(
             s.s_lo = sf[b];
         }
         tab[t1] = s;
+        // u = (t1 - 1 - lo + frac) inv_span, so mu = m_lo + dm u is a line in frac
+        const double u0 = double(t1 - 1 - s.lo) * s.inv_span;
         ws.tablef[int64_t(f) * (n_bins + 1) + t1] =
-            SegF{float(s.m_lo), float(s.dm), float(s.s_lo), float(s.ds), float(s.inv_span), s.lo};
+            SegF{float(s.m_lo + s.dm * u0), float(s.dm * s.inv_span), float(s.s_lo + s.ds * u0),
+                 float(s.ds * s.inv_span)};
     }
     if (tid == 0) {
         if (n_kept) n_kept[f] = 0;
@@ -215,26 +219,28 @@ __device__ inline uint8_t pixel_bits(float x, uint32_t rc, bool masked, const Se
 }
 
 // Float32 version of pixel_bits.  Its rounding errors are below 1e-6 of the
-// scale |v| + |mu| + sigma terms, so when v - mu is further than 1e-5 of that
-// scale from both thresholds its decisions are those of the float64
-// computation; otherwise the pixel is decided again in float64.
-__device__ inline uint8_t pixel_bits_fast(float x, uint32_t rc, const SegF &sg, const Seg *__restrict__ tab,
-                                          int n_bins, float noise2f, double noise2, float n_pick_f, float snr_f,
-                                          double n_pick, double snr) {
-    if (rc == SS_RC_MASKED || !isfinite(x)) return 0;
-    const int t1 = min(int(rc >> SS_RC_FRAC_BITS), n_bins);
-    const float frac = float(rc & ((1u << SS_RC_FRAC_BITS) - 1u)) * (1.0f / float(1u << SS_RC_FRAC_BITS));
-    const float u = (float(t1 - 1 - sg.lo) + frac) * sg.inv_span;
-    const float mu = fmaf(sg.dm, u, sg.m_lo);
-    const float sd = fmaf(sg.ds, u, sg.s_lo);
-    const float se = noise2f == 0.0f ? fabsf(sd) : sqrtf(fmaf(sd, sd, noise2f));
+// scale |v| + |a| + |b| + |c| + |d| + sigma (a + b frac and c + d frac are
+// the interval's lines, |frac| < 1), so when v - mu is further than 1e-5 of
+// that scale from both thresholds its decisions are those of the float64
+// computation; otherwise it returns kUndecided and the pixel is decided
+// again in float64 (pixel_bits).
+constexpr uint8_t kUndecided = 0xFF;
+
+// frac: the pixel's position in its interval, NaN for a masked pixel.
+// Branch free: every slot's arithmetic runs, the result is selected.
+__device__ inline uint8_t pixel_bits_fast(float x, float frac, const SegF &sg, float noise2f, float n_pick_f,
+                                          float snr_f) {
+    const bool valid = frac == frac && __builtin_isfinite(x);
+    const float mu = fmaf(sg.b, frac, sg.a);
+    const float sd = fmaf(sg.d, frac, sg.c);
+    // the hardware square root (within 1 ulp) is far inside the tolerance
+    const float se = noise2f == 0.0f ? fabsf(sd) : __builtin_amdgcn_sqrtf(fmaf(sd, sd, noise2f));
     const float d = x - mu;
     const float tk = n_pick_f * se, tc = snr_f * se;
-    const float tol = 1e-5f * (fabsf(x) + fabsf(sg.m_lo) + fabsf(sg.dm) + fabsf(sg.s_lo) + fabsf(sg.ds) + se) +
-                      1e-30f;
-    if (fabsf(d - tk) <= tol || fabsf(d - tc) <= tol)
-        return pixel_bits(x, rc, false, tab, n_bins, noise2, n_pick, snr);
-    return kValid | (d > tk ? kKeep : 0) | (d >= tc ? kCand : 0);
+    const float tol = 1e-5f * (fabsf(x) + fabsf(sg.a) + fabsf(sg.b) + fabsf(sg.c) + fabsf(sg.d) + se) + 1e-30f;
+    const bool near = fabsf(d - tk) <= tol || fabsf(d - tc) <= tol;
+    const uint32_t bits = kValid | (d > tk ? kKeep : 0u) | (d >= tc ? kCand : 0u);
+    return uint8_t(valid ? (near ? uint32_t(kUndecided) : bits) : 0u);
 }
 
 // 2-D stencil tile (core pixels), work-group size and frames per
@@ -250,7 +256,10 @@ __device__ inline uint8_t pixel_bits_fast(float x, uint32_t rc, const SegF &sg, 
 #endif
 constexpr int kTileH = SS_STENCIL_TILE_H;
 constexpr int kTileW = SS_STENCIL_TILE_W;
-constexpr int kStencilBlock = 256;
+#ifndef SS_STENCIL_BLOCK
+#define SS_STENCIL_BLOCK 256
+#endif
+constexpr int kStencilBlock = SS_STENCIL_BLOCK;
 constexpr int kFramesPerBlock = SS_STENCIL_FRAMES;
 // staged pixels per thread for a halo of h pixels
 constexpr int stage_slots(int h) { return ((kTileH + 2 * h) * (kTileW + 2 * h) + kStencilBlock - 1) / kStencilBlock; }
@@ -337,9 +346,10 @@ __global__ __launch_bounds__(kStencilBlock) void k_pixel_state(StateArgs a) {
     extern __shared__ unsigned char lds[];
     const int h = a.half;
     const int RW = kTileW + 2 * h, RH = kTileH + 2 * h, RN = RW * RH;
+    // radial codes once; values and pixel bits double-buffered by frame
     uint32_t *rc_s = reinterpret_cast<uint32_t *>(lds);
-    float *v_s = reinterpret_cast<float *>(lds + size_t(RN) * 4);
-    uint8_t *b_s = lds + size_t(RN) * 8;
+    float *v_base = reinterpret_cast<float *>(lds + size_t(RN) * 4);
+    uint8_t *b_base = lds + size_t(RN) * 12;
 
     const int tx0 = blockIdx.x * kTileW, ty0 = blockIdx.y * kTileH;
     const int f0 = blockIdx.z * kFramesPerBlock;
@@ -360,54 +370,108 @@ __global__ __launch_bounds__(kStencilBlock) void k_pixel_state(StateArgs a) {
         rc_s[e] = rc;
     }
     __syncthreads();
+    // Per staged slot, fixed over the frames: the pixel's byte offset in a
+    // frame (clamped into the frame; out-of-frame and padding slots are
+    // masked), its interval's byte offset in a frame's float32 table, and
+    // its fraction of the interval (NaN when masked).  Frames hold fewer
+    // than 2^29 pixels, so byte offsets fit 32 bits.
+    uint32_t voff[kStageSlots], toff[kStageSlots];
+    float frac[kStageSlots];
+#pragma unroll
+    for (int k = 0; k < kStageSlots; ++k) {
+        const int e = tid + k * kStencilBlock;
+        const int ec = min(e, RN - 1);
+        const int r = int((uint32_t(ec) * magic) >> 20);
+        const int y = min(max(ty0 - h + r, 0), a.height - 1);
+        const int x = min(max(tx0 - h + (ec - r * RW), 0), a.width - 1);
+        voff[k] = (uint32_t(y) * uint32_t(a.width) + uint32_t(x)) * 4u;
+        const uint32_t rc = e < RN ? rc_s[e] : SS_RC_MASKED;
+        toff[k] = uint32_t(min(int(rc >> SS_RC_FRAC_BITS), a.n_bins)) * uint32_t(sizeof(SegF));
+        frac[k] = rc == SS_RC_MASKED ? __builtin_nanf("")
+                                     : float(rc & ((1u << SS_RC_FRAC_BITS) - 1u)) * (1.0f / float(1u << SS_RC_FRAC_BITS));
+    }
+    // the tile's core pixels this thread tests and writes: LDS index and
+    // offset in a frame (kNoPixel outside the frame)
+    constexpr int kCore = kTileH * kTileW / kStencilBlock;
+    static_assert(kTileH * kTileW % kStencilBlock == 0, "whole core pixels per thread");
+    constexpr uint32_t kNoPixel = 0xFFFFFFFFu;
+    uint32_t soff[kCore];
+    int cidx[kCore];
+#pragma unroll
+    for (int j = 0; j < kCore; ++j) {
+        const int c = tid + j * kStencilBlock;
+        const int ly = c / kTileW, lx = c % kTileW;
+        const int y = ty0 + ly, x = tx0 + lx;
+        soff[j] = (y < a.height && x < a.width) ? uint32_t(y) * uint32_t(a.width) + uint32_t(x) : kNoPixel;
+        cidx[j] = (ly + h) * RW + (lx + h);
+    }
 
+    // Frame f's values are loaded while frame f - 1 is classified and its
+    // patches tested (one frame ahead), and the two LDS buffers alternate,
+    // so one barrier per frame separates staging from the patch test: a
+    // thread stages frame f + 1 only after the barrier of frame f, which
+    // every thread reaches after its patch tests of frame f - 1.
+    const uint32_t frame_bytes = uint32_t(a.n_pix) * 4u;
+    const uint32_t table_bytes = uint32_t(a.n_bins + 1) * uint32_t(sizeof(SegF));
+    float xv[kStageSlots];
+    if (f0 < f1) {
+        const __amdgpu_buffer_rsrc_t rf = buffer_rsrc(a.frames + int64_t(f0) * a.n_pix, frame_bytes);
+#pragma unroll
+        for (int k = 0; k < kStageSlots; ++k) xv[k] = buffer_load_f32(rf, voff[k], 0u);
+    }
     for (int f = f0; f < f1; ++f) {
-        const float *__restrict__ fr = a.frames + int64_t(f) * a.n_pix;
-        const Seg *__restrict__ tab = a.ws.table + int64_t(f) * (a.n_bins + 1);
-        const SegF *__restrict__ tabf = a.ws.tablef + int64_t(f) * (a.n_bins + 1);
-        // Staging in three sweeps so that a thread's loads overlap: every
-        // frame value (clamped addresses, masked after), then every table
-        // segment, then the arithmetic.
-        float xv[kStageSlots];
-        uint32_t rcv[kStageSlots];
+        float *v_s = v_base + ((f - f0) & 1) * RN;
+        uint8_t *b_s = b_base + ((f - f0) & 1) * RN;
+        uint8_t bv[kStageSlots];
+        {
+            const __amdgpu_buffer_rsrc_t rt = buffer_rsrc(a.ws.tablef + int64_t(f) * (a.n_bins + 1), table_bytes);
+            SegF sg[kStageSlots];
 #pragma unroll
-        for (int k = 0; k < kStageSlots; ++k) {
-            const int e = tid + k * kStencilBlock;
-            const int ec = min(e, RN - 1);
-            const int r = int((uint32_t(ec) * magic) >> 20);
-            const int y = min(max(ty0 - h + r, 0), a.height - 1);
-            const int x = min(max(tx0 - h + (ec - r * RW), 0), a.width - 1);
-            rcv[k] = e < RN ? rc_s[ec] : SS_RC_MASKED;
-            xv[k] = fr[int64_t(y) * a.width + x];
+            for (int k = 0; k < kStageSlots; ++k) {
+                // (element access on the builtin's vector result is not used:
+                // copying the whole vector out keeps the 16-byte load intact)
+                const auto q = __builtin_amdgcn_raw_buffer_load_b128(rt, int(toff[k]), 0, 0);
+                __builtin_memcpy(&sg[k], &q, sizeof(SegF));
+            }
+#pragma unroll
+            for (int k = 0; k < kStageSlots; ++k) bv[k] = pixel_bits_fast(xv[k], frac[k], sg[k], a.noise2f, a.n_pick_f,
+                                                                          a.snr_f);
         }
-        SegF sg[kStageSlots];
+        // pixels within rounding of a threshold, in float64 (rare; the
+        // float32 table entries are no longer live here)
+        bool undecided = false;
 #pragma unroll
-        for (int k = 0; k < kStageSlots; ++k) sg[k] = tabf[min(int(rcv[k] >> SS_RC_FRAC_BITS), a.n_bins)];
+        for (int k = 0; k < kStageSlots; ++k) undecided = undecided || bv[k] == kUndecided;
+        if (__builtin_amdgcn_ballot_w64(undecided) != 0) {
+            const Seg *__restrict__ tab = a.ws.table + int64_t(f) * (a.n_bins + 1);
+#pragma unroll
+            for (int k = 0; k < kStageSlots; ++k)
+                if (bv[k] == kUndecided)
+                    bv[k] = pixel_bits(xv[k], rc_s[tid + k * kStencilBlock], false, tab, a.n_bins, a.noise2, a.n_pick,
+                                       a.snr);
+        }
 #pragma unroll
         for (int k = 0; k < kStageSlots; ++k) {
             const int e = tid + k * kStencilBlock;
-            if (e < RN) {
-                const uint32_t rc = rcv[k];
-                uint8_t b = 0;
-                if (rc != SS_RC_MASKED)
-                    b = pixel_bits_fast(xv[k], rc, sg[k], tab, a.n_bins, a.noise2f, a.noise2, a.n_pick_f, a.snr_f,
-                                        a.n_pick, a.snr);
-                v_s[e] = rc != SS_RC_MASKED ? xv[k] : 0.0f;
-                b_s[e] = b;
+            if (k < kStageSlots - 1 || e < RN) {
+                v_s[e] = frac[k] == frac[k] ? xv[k] : 0.0f;
+                b_s[e] = bv[k];
             }
         }
-        __syncthreads();
-        uint8_t *__restrict__ bits = a.ws.bits + int64_t(f) * a.n_pix;
-        for (int c = tid; c < kTileH * kTileW; c += kStencilBlock) {
-            const int ly = c / kTileW, lx = c % kTileW;
-            const int y = ty0 + ly, x = tx0 + lx;
-            if (y >= a.height || x >= a.width) continue;
-            const int e = (ly + h) * RW + (lx + h);
-            uint8_t b = b_s[e];
-            if ((b & kCand) && patch_is_peak<kH>(v_s, b_s, e, RW, h, a.min_count)) b |= kPeak;
-            bits[int64_t(y) * a.width + x] = b;
+        if (f + 1 < f1) {
+            const __amdgpu_buffer_rsrc_t rf = buffer_rsrc(a.frames + int64_t(f + 1) * a.n_pix, frame_bytes);
+#pragma unroll
+            for (int k = 0; k < kStageSlots; ++k) xv[k] = buffer_load_f32(rf, voff[k], 0u);
         }
         __syncthreads();
+        const __amdgpu_buffer_rsrc_t rb = buffer_rsrc(a.ws.bits + int64_t(f) * a.n_pix, uint32_t(a.n_pix));
+#pragma unroll
+        for (int j = 0; j < kCore; ++j) {
+            const int e = cidx[j];
+            uint8_t b = b_s[e];
+            if ((b & kCand) && patch_is_peak<kH>(v_s, b_s, e, RW, h, a.min_count)) b |= kPeak;
+            if (soff[j] != kNoPixel) __builtin_amdgcn_raw_buffer_store_b8(b, rb, int(soff[j]), 0, 0);
+        }
     }
 }
 
@@ -791,7 +855,7 @@ extern "C" int ss_classify(const float *frames, const uint8_t *mask, int32_t n_f
     if (!radial || !profile || !p) return SS_EINVAL;
     if (n_frames < 0 || height < 0 || width < 0 || capacity < 0 || peak_capacity < 0) return SS_ESIZE;
     const int64_t n_pix = int64_t(height) * width;
-    if (n_pix >= (int64_t(1) << 31) || n_frames > 65535) return SS_ESIZE;
+    if (n_pix >= (int64_t(1) << 29) || n_frames > 65535) return SS_ESIZE;
     if (radial->n_bins <= 0 || radial->n_bins > SS_MAX_BINS) return SS_ESIZE;
     if (p->patch < 1 || p->patch > SS_MAX_PATCH || (p->patch % 2) == 0) return SS_EINVAL;
     const bool keep = kept_index || kept_value || n_kept;
@@ -830,7 +894,7 @@ extern "C" int ss_classify(const float *frames, const uint8_t *mask, int32_t n_f
         sa.snr_f = p->snr;
         sa.ws = ws;
         const int h = sa.half;
-        const size_t lds = size_t(kTileW + 2 * h) * size_t(kTileH + 2 * h) * 9;
+        const size_t lds = size_t(kTileW + 2 * h) * size_t(kTileH + 2 * h) * 14;
         const dim3 grid(uint32_t((width + kTileW - 1) / kTileW), uint32_t((height + kTileH - 1) / kTileH),
                         uint32_t((n_frames + kFramesPerBlock - 1) / kFramesPerBlock));
         // staging registers sized to the halo; patches 1, 3 and 5 unrolled
