@@ -275,6 +275,7 @@ struct StateArgs {
     int32_t half, min_count;
     double noise2, n_pick, snr;
     float noise2f, n_pick_f, snr_f;
+    int32_t tiles_x, tiles_y, frame_groups;
     Workspace ws;
 };
 
@@ -351,8 +352,22 @@ __global__ __launch_bounds__(kStencilBlock) void k_pixel_state(StateArgs a) {
     float *v_base = reinterpret_cast<float *>(lds + size_t(RN) * 4);
     uint8_t *b_base = lds + size_t(RN) * 12;
 
-    const int tx0 = blockIdx.x * kTileW, ty0 = blockIdx.y * kTileH;
-    const int f0 = blockIdx.z * kFramesPerBlock;
+    // Work-groups go to the 8 XCDs round robin; work-group g takes item
+    // (g % 8) * per + g / 8 of the row-major list (frame group, tile row,
+    // tile column), so each XCD walks a contiguous run of tiles and the
+    // halo cache lines that neighbouring tiles share are fetched into one L2.
+    int tx0, ty0, f0;
+    {
+        const uint32_t total = uint32_t(a.tiles_x) * uint32_t(a.tiles_y) * uint32_t(a.frame_groups);
+        const uint32_t per = (total + 7u) / 8u;
+        const uint32_t g = blockIdx.x;
+        const uint32_t item = (g % 8u) * per + g / 8u;
+        if (g / 8u >= per || item >= total) return;
+        const uint32_t row = item / uint32_t(a.tiles_x);
+        tx0 = int(item - row * uint32_t(a.tiles_x)) * kTileW;
+        ty0 = int(row % uint32_t(a.tiles_y)) * kTileH;
+        f0 = int(row / uint32_t(a.tiles_y)) * kFramesPerBlock;
+    }
     const int f1 = min(a.n_frames, f0 + kFramesPerBlock);
     const int tid = threadIdx.x;
     // e / RW as (e * magic) >> 20, exact for e < 2^20 / RW (RN is far smaller)
@@ -895,8 +910,13 @@ extern "C" int ss_classify(const float *frames, const uint8_t *mask, int32_t n_f
         sa.ws = ws;
         const int h = sa.half;
         const size_t lds = size_t(kTileW + 2 * h) * size_t(kTileH + 2 * h) * 14;
-        const dim3 grid(uint32_t((width + kTileW - 1) / kTileW), uint32_t((height + kTileH - 1) / kTileH),
-                        uint32_t((n_frames + kFramesPerBlock - 1) / kFramesPerBlock));
+        sa.tiles_x = (width + kTileW - 1) / kTileW;
+        sa.tiles_y = (height + kTileH - 1) / kTileH;
+        sa.frame_groups = (n_frames + kFramesPerBlock - 1) / kFramesPerBlock;
+        const int64_t items = int64_t(sa.tiles_x) * sa.tiles_y * sa.frame_groups;
+        if (items == 0) return SS_OK;
+        if (items > (int64_t(1) << 31)) return SS_ESIZE;
+        const dim3 grid(uint32_t(8 * ((items + 7) / 8)));
         // staging registers sized to the halo; patches 1, 3 and 5 unrolled
         if (h == 0) k_pixel_state<stage_slots(0), 0><<<grid, kStencilBlock, lds, stream>>>(sa);
         else if (h == 1) k_pixel_state<stage_slots(1), 1><<<grid, kStencilBlock, lds, stream>>>(sa);

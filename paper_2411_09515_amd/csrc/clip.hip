@@ -159,22 +159,49 @@ __device__ inline void add_member(double (&s)[NSUM], double w, double d, double 
     s[S_N] += 1.0;
 }
 
-// Work-group -> (frame, bin), or (group of fpi frames, bin).  Work-groups are dispatched to the 8 XCDs
-// round robin (work-group g runs on XCD g % 8), so work-group g is given the
-// item x * per + g / 8 of the frame-major list (frame, bin), x = g % 8: each
-// XCD walks a contiguous run of that list, and neighbouring bins of a frame,
-// whose rings share cache lines, run back to back on the same L2.  Returns
+// Work-group -> (frame, bin), or (group of fpi frames, bin).  Work-groups are
+// dispatched to the 8 XCDs round robin (work-group g runs on XCD g % 8), so
+// work-group g is given item x * per + g / 8 of an ordered item list,
+// x = g % 8: each XCD walks a contiguous run of that list.  The list is
+// tiled: kTileFrames frame groups by kTileBins bins at a time, frame-major
+// inside a tile, tiles bin-major inside a run of kTileFrames frame groups.
+// The work-groups an XCD holds at once then cover a few neighbouring bins of
+// a few frames: neighbouring bins share the cache lines of their rings
+// (gathers), and the frames of one bin share its CSR row, so both are read
+// from HBM about once per tile instead of once per work-group.  Returns
 // false for the padding work-groups beyond the list.
+#ifndef SS_CLIP_TILE_FRAMES
+#define SS_CLIP_TILE_FRAMES 1
+#endif
+#ifndef SS_CLIP_TILE_BINS
+#define SS_CLIP_TILE_BINS 8
+#endif
+constexpr uint32_t kTileFrames = SS_CLIP_TILE_FRAMES;
+constexpr uint32_t kTileBins = SS_CLIP_TILE_BINS;
+
+__device__ inline void tile_item(uint32_t item, uint32_t nfg, uint32_t nb, uint32_t &fg, uint32_t &local) {
+    const uint32_t ft = item / (kTileFrames * nb);
+    const uint32_t gt = min(kTileFrames, nfg - ft * kTileFrames);
+    const uint32_t rem = item - ft * kTileFrames * nb;
+    const uint32_t bt = rem / (gt * kTileBins);
+    const uint32_t btn = min(kTileBins, nb - bt * kTileBins);
+    const uint32_t r2 = rem - bt * gt * kTileBins;
+    fg = ft * kTileFrames + r2 / btn;
+    local = bt * kTileBins + r2 % btn;
+}
+
 __device__ inline bool block_item(const ClipArgs &a, int fpi, int &f, int &bin) {
     const uint32_t nb = uint32_t(a.launch_bins);
-    const uint32_t total = uint32_t((a.n_frames + fpi - 1) / fpi) * nb;
+    const uint32_t nfg = uint32_t((a.n_frames + fpi - 1) / fpi);
+    const uint32_t total = nfg * nb;
     const uint32_t per = (total + 7u) / 8u;
     const uint32_t g = blockIdx.x;
     const uint32_t item = (g % 8u) * per + g / 8u;
     if (g / 8u >= per || item >= total) return false;
-    f = int(item / nb);
-    const int local = int(item % nb);
-    bin = a.bin_order ? a.bin_order[a.order_base + local] : local;
+    uint32_t fg, local;
+    tile_item(item, nfg, nb, fg, local);
+    f = int(fg);
+    bin = a.bin_order ? a.bin_order[a.order_base + int(local)] : int(local);
     return uint32_t(bin) < uint32_t(a.n_bins);
 }
 
@@ -583,8 +610,11 @@ __device__ __forceinline__ void clip_body(const ClipArgs &a, int g, int bin) {
             for (int f = 0; f < FB; ++f) {
                 const float x = SS_V(f, e);
                 const bool ok = entry_ok && (f < nf) && __builtin_isfinite(x);
-                const float wz = ok ? w : 0.0f;
-                const float xz = ok ? x : 0.0f;
+                float wz = ok ? w : 0.0f;
+                float xz = ok ? x : 0.0f;
+                // select in float32, then widen (one select per operand
+                // instead of one per half of its float64 widening)
+                asm("" : "+v"(wz), "+v"(xz));
                 t[3 * f + 0] += double(wz);
                 t[3 * f + 1] = fma(double(wz), double(xz), t[3 * f + 1]);
                 n_ok[f] += ok ? 1 : 0;
@@ -756,7 +786,7 @@ __device__ __forceinline__ void clip_body(const ClipArgs &a, int g, int bin) {
 #pragma unroll
                     for (int e = 0; e < EPT; ++e) {
                         const bool out = !(SUR && ((gone[f] >> e) & 1u)) && clipped(SS_V(f, e), bnd);
-                        const uint64_t m = __ballot(out);
+                        const uint64_t m = __builtin_amdgcn_ballot_w64(out);
                         if (m == 0) continue;
                         const int cnt = __popcll(m);
                         if (used + cnt > kRemCap) {

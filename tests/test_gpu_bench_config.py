@@ -1,0 +1,85 @@
+"""The throughput benchmark's own launch configuration against the FP64
+oracle, through the C ABI: one call per stage on 64 raw Jungfrau-4M frames
+(2162 x 2068, 1000 bins, bounding-box splitting), so every row-length class
+runs with its default work-group shape and several frames per work-group.
+
+* sampled frames of the batch (first, middle, last) match the oracle: the
+  correction bit for bit, the profile and the kept pixels / peaks at the
+  tolerances of ``parity``;
+* frames are independent inside the batch: the batch holds 16 distinct
+  frames four times over (neighbouring frames always differ), and every
+  repeat gives bit-identical results wherever it sits in the batch.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from paper_2411_09515_amd import api
+
+from parity import OracleScene
+from test_gpu_parity import _check_classify
+
+pytestmark = pytest.mark.gpu
+
+N_DISTINCT, N_FRAMES = 16, 64
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def batch(dev):
+    g = synth.JUNGFRAU4M
+    _say("setup: 16 distinct jungfrau-4m frames (~10 s) and the oracle geometry")
+    distinct = synth.jungfrau_frames(g, N_DISTINCT).reshape(N_DISTINCT, -1)
+    raw = np.concatenate([distinct] * (N_FRAMES // N_DISTINCT))
+    sc = OracleScene(g)
+    geo = api.Geometry.from_scene(g, synth.stripe_mask(g), synth.normalisation(g), dev)
+    ped, gain = (torch.from_numpy(np.array(a)).to(dev) for a in synth.jungfrau_calibration(g))
+    p = api.Params()
+    pipe = api.Pipeline(geo, p, N_FRAMES, ped, gain, kept_capacity=1 << 18, peak_capacity=1 << 13, device=dev)
+    _say("case: whole path on 64 frames (benchmark shapes)")
+    out = pipe.run(torch.from_numpy(raw).to(dev))
+    torch.cuda.synchronize()
+    return g, sc, raw, pipe, out, p
+
+
+@pytest.mark.parametrize("f", [0, 37, 63])
+def test_sampled_frames_match_oracle(dev, batch, f):
+    g, sc, raw, pipe, out, p = batch
+    _say(f"case: 64-frame batch, frame {f} vs oracle")
+    frames, _ = sc.frames_from_raw(raw[f:f + 1])
+    got = pipe.frames[f].cpu().numpy()
+    assert np.array_equal(got.view(np.uint32), frames[0].view(np.uint32))
+    nd, npd, nk, npk = _check_classify(sc, frames[0], pipe.profile, f, out, p, f"bench batch frame {f}")
+    _say(f"  frame {f}: kept {nk} (band diffs {nd}), peaks {npk} (band diffs {npd})")
+
+
+def test_repeated_frames_are_identical(dev, batch):
+    g, sc, raw, pipe, out, p = batch
+    _say("case: 64-frame batch, repeats bit for bit")
+    prof = {k: v.cpu() for k, v in pipe.profile.items()}
+    n_kept, n_peaks = out["n_kept"].cpu(), out["n_peaks"].cpu()
+    for f in range(N_DISTINCT):
+        for r in range(f + N_DISTINCT, N_FRAMES, N_DISTINCT):
+            assert torch.equal(pipe.frames[f], pipe.frames[r]), (f, r)
+            for k, v in prof.items():
+                assert torch.equal(v[f], v[r]), (k, f, r)
+            assert n_kept[f] == n_kept[r] and n_peaks[f] == n_peaks[r], (f, r)
+            n, m = int(n_kept[f]), int(n_peaks[f])
+            assert torch.equal(out["kept_index"][f, :n], out["kept_index"][r, :n])
+            assert torch.equal(out["kept_value"][f, :n], out["kept_value"][r, :n])
+            assert torch.equal(out["peaks"][f, :m], out["peaks"][r, :m])
