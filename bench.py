@@ -159,16 +159,21 @@ def batched_uneven(api, torch, uneven, dev, cache, reps=10):
             "frames_per_s": round(n / graph_ms * 1e3, 1), "autotuned_shapes": best}
 
 
-def serving(api, serve, torch, rings, dev, cache, loads=((1000, 1.0), (2000, 1.0))):
+def serving(api, serve, torch, rings, dev, cache, loads=((1000, 1.0), (2000, 1.0), (4000, 1.0))):
     """Poisson arrivals from 1M/4M/9M/16M detectors into device rings, served
     with continuous batching; per-frame latency from arrival to results on the host."""
     dets = []
     for (name, _), ring in zip(SERVE, rings):
         geo, ped, gain = _geometry(api, torch, name, dev, cache)
         dets.append(serve.Detector(name, geo, ped, gain, torch.from_numpy(ring.view(np.int16)).to(dev),
-                                   api.Params(cutoff=3.0, max_iter=5), max_batch=8))
+                                   api.Params(cutoff=3.0, max_iter=5), max_batch=16))
     server = serve.Server(dets, hbm_budget=24 << 30, device=dev)
     server.warmup()
+    # steady state before measuring: one throwaway run as large as the largest
+    # measured one, so that the host memory the results land in is already mapped
+    total, dur = max(loads)
+    server.run(serve.poisson_arrivals([total * f for _, f in SERVE], dur, [SERVE_RING] * len(SERVE), seed=1),
+               realtime=True)
     out = []
     for total, dur in loads:
         reqs = serve.poisson_arrivals([total * f for _, f in SERVE], dur, [SERVE_RING] * len(SERVE), seed=total)
@@ -178,8 +183,11 @@ def serving(api, serve, torch, rings, dev, cache, loads=((1000, 1.0), (2000, 1.0
                     "latency_ms": {k: round(v, 3) for k, v in st["latency_ms"].items()},
                     "mean_batch": round(st["mean_batch"], 2), "max_waiting": st["max_waiting"],
                     "max_batches_in_flight": st["max_batches_in_flight"]})
-    return {"detectors": [n for n, _ in SERVE], "hbm_reserved_bytes": server.reserved_bytes,
-            "slots_per_detector": server.slots_per_detector, "runs": out}
+        del done, reqs   # a consumer keeps results only until they are stored
+    res = {"detectors": [n for n, _ in SERVE], "hbm_reserved_bytes": server.reserved_bytes,
+           "slots_per_detector": server.slots_per_detector, "max_batch": 16, "graphs": True, "runs": out}
+    server.close()
+    return res
 
 
 def surrogate_vs_plain(api, torch, geo, pipe, train_raw, frames, steps, reps=5):

@@ -402,6 +402,29 @@ int ss_densify(const uint32_t *kept_index, const float *kept_value, int64_t capa
 int ss_veto(const int64_t *n_peaks, const int64_t *n_kept, int32_t n_frames, int64_t threshold,
             uint8_t *hit, int64_t *counters, hipStream_t stream);
 
+/*
+ * ss_pack_results -- the kept entries and peaks of n_frames frames packed
+ * back to back, so that a caller returning results to the host copies one
+ * contiguous prefix per kind instead of one piece per frame (serving
+ * support; not a step of the paper's method).
+ * Frame f contributes its first min(n_kept[f], capacity) entries of
+ * kept_index / kept_value (ss_compress layout) and its first
+ * min(n_peaks[f], peak_capacity) peaks, in frame order.
+ *   offsets [dev] int64 [2 (n_frames + 1)]: written; offsets[f] is frame f's
+ *     first packed entry, offsets[n_frames] their total; offsets[n_frames +
+ *     1 + f] and offsets[2 n_frames + 1] the same for peaks
+ *   packed_index, packed_value [dev] >= n_frames * capacity entries,
+ *   packed_peaks [dev] >= n_frames * peak_capacity records
+ *   either group (kept: kept_index, kept_value, n_kept, packed_index,
+ *   packed_value; peaks: peaks, n_peaks, packed_peaks) may be all NULL; its
+ *   offsets are then 0.
+ * Errors: SS_EINVAL, SS_ESIZE, SS_EHIP.
+ */
+int ss_pack_results(const uint32_t *kept_index, const float *kept_value, int64_t capacity,
+                    const int64_t *n_kept, const ss_peak *peaks, int64_t peak_capacity,
+                    const int64_t *n_peaks, int32_t n_frames, int64_t *offsets, uint32_t *packed_index,
+                    float *packed_value, ss_peak *packed_peaks, hipStream_t stream);
+
 /* ------------------------------------------------------------------------
  * Learned clip surrogate.  Not in the paper: the paper's clip time grows
  * with the number of passes (Sec. 2.4); a small network predicts each bin's

@@ -478,6 +478,29 @@ def veto_summary(counters):
                 hist_frames=c[4:4 + nb].copy(), hist_kept=c[4 + nb:4 + 2 * nb].copy())
 
 
+def pack_results(out, capacity, peak_capacity, packed=None):
+    """Kept entries and peaks of the frames of ``out`` (the dict ``classify``
+    fills) packed back to back on the device; returns the dict of packed
+    buffers with ``offsets`` [2 (F + 1)] (kept, then peaks)."""
+    F = out["n_kept"].shape[0] if "n_kept" in out else out["n_peaks"].shape[0]
+    dev = (out.get("n_kept") if out.get("n_kept") is not None else out["n_peaks"]).device
+    if packed is None:
+        packed = dict(offsets=torch.empty(2 * (F + 1), dtype=torch.int64, device=dev),
+                      index=torch.empty(max(F * capacity, 1), dtype=torch.int32, device=dev),
+                      value=torch.empty(max(F * capacity, 1), dtype=torch.float32, device=dev),
+                      peaks=torch.empty((max(F * peak_capacity, 1), B.PEAK_BYTES), dtype=torch.uint8, device=dev))
+    keep = out.get("n_kept") is not None
+    pk = out.get("n_peaks") is not None
+    _need_device(*(v for v in out.values()), *(v for v in packed.values()))
+    B.check("ss_pack_results", B.lib().ss_pack_results(
+        _p(out.get("kept_index")) if keep else None, _p(out.get("kept_value")) if keep else None, capacity,
+        _p(out.get("n_kept")) if keep else None, _p(out.get("peaks")) if pk else None, peak_capacity,
+        _p(out.get("n_peaks")) if pk else None, F, _p(packed["offsets"]),
+        _p(packed["index"]) if keep else None, _p(packed["value"]) if keep else None,
+        _p(packed["peaks"]) if pk else None, _stream()))
+    return packed
+
+
 def peaks_to_numpy(peaks_u8, n):
     """Host copy of the first n peak records of one frame as a structured array."""
     raw = peaks_u8[: max(int(n), 0)].cpu().numpy()

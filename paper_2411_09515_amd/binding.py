@@ -39,7 +39,7 @@ EXPORTED = (
     "ss_compress", "ss_peakfind",
     "ss_clip_features", "ss_surrogate_targets", "ss_mlp_forward", "ss_mlp_grad_workspace", "ss_mlp_grad",
     "ss_mlp_adam", "ss_sigma_clip_surrogate", "ss_sigma_clip_batches",
-    "ss_densify_workspace", "ss_densify", "ss_veto",
+    "ss_densify_workspace", "ss_densify", "ss_veto", "ss_pack_results",
 )
 
 
@@ -154,6 +154,8 @@ def lib():
         L.ss_densify.argtypes = [vp, vp, i64, vp, vp, i32, i64, P(Radial), P(Profile), P(Noise), vp, vp, sz, vp]
         L.ss_veto.restype = ctypes.c_int
         L.ss_veto.argtypes = [vp, vp, i32, i64, vp, vp, vp]
+        L.ss_pack_results.restype = ctypes.c_int
+        L.ss_pack_results.argtypes = [vp, vp, i64, vp, vp, i64, vp, i32, vp, vp, vp, vp, vp]
         _lib = L
     return _lib
 

@@ -853,6 +853,89 @@ __global__ __launch_bounds__(kVetoBlock) void k_veto(const int64_t *__restrict__
     atomicAdd(counters + 4 + SS_VETO_BINS + b, k);
 }
 
+
+// ---- packed results ------------------------------------------------------------------------
+
+constexpr int kPackBlock = 256;
+
+// Exclusive offsets of the kept entries and peaks each frame returns
+// (counts clamped to the capacities): offsets[0..F] for kept entries,
+// offsets[F+1..2F+1] for peaks.  One work-group walks the frames in order.
+__global__ __launch_bounds__(kPackBlock) void k_pack_offsets(const int64_t *__restrict__ n_kept, int64_t capacity,
+                                                             const int64_t *__restrict__ n_peaks,
+                                                             int64_t peak_capacity, int32_t n_frames,
+                                                             int64_t *__restrict__ offsets) {
+    __shared__ int64_t carry[2];
+    __shared__ int64_t part[2][kPackBlock / kWave];
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
+    if (tid == 0) carry[0] = carry[1] = 0;
+    __syncthreads();
+    for (int base = 0; base < n_frames; base += kPackBlock) {
+        const int f = base + tid;
+        int64_t v[2] = {0, 0};
+        if (f < n_frames) {
+            v[0] = n_kept ? min(max(n_kept[f], int64_t(0)), capacity) : 0;
+            v[1] = n_peaks ? min(max(n_peaks[f], int64_t(0)), peak_capacity) : 0;
+        }
+        int64_t incl[2] = {v[0], v[1]};
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int off = 1; off < kWave; off <<= 1) {
+                const int64_t t = __shfl_up(incl[q], off, kWave);
+                if (lane >= off) incl[q] += t;
+            }
+        if (lane == kWave - 1) {
+            part[0][wid] = incl[0];
+            part[1][wid] = incl[1];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            int64_t before = carry[q];
+            for (int w = 0; w < wid; ++w) before += part[q][w];
+            if (f < n_frames) offsets[int64_t(q) * (n_frames + 1) + f] = before + incl[q] - v[q];
+        }
+        __syncthreads();
+        if (tid == 0) {
+            for (int w = 0; w < kPackBlock / kWave; ++w) {
+                carry[0] += part[0][w];
+                carry[1] += part[1][w];
+            }
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        offsets[n_frames] = carry[0];
+        offsets[2 * int64_t(n_frames) + 1] = carry[1];
+    }
+}
+
+// Frame f's first min(n, capacity) kept entries and peaks to their packed
+// positions.
+__global__ __launch_bounds__(kPackBlock) void k_pack_copy(const uint32_t *__restrict__ kept_index,
+                                                          const float *__restrict__ kept_value, int64_t capacity,
+                                                          const ss_peak *__restrict__ peaks, int64_t peak_capacity,
+                                                          int32_t n_frames, const int64_t *__restrict__ offsets,
+                                                          uint32_t *__restrict__ packed_index,
+                                                          float *__restrict__ packed_value,
+                                                          ss_peak *__restrict__ packed_peaks) {
+    const int f = blockIdx.y;
+    const int64_t stride = int64_t(gridDim.x) * kPackBlock;
+    const int64_t t0 = int64_t(blockIdx.x) * kPackBlock + threadIdx.x;
+    if (packed_index) {
+        const int64_t o = offsets[f], n = offsets[f + 1] - o;
+        for (int64_t k = t0; k < n; k += stride) {
+            packed_index[o + k] = kept_index[int64_t(f) * capacity + k];
+            packed_value[o + k] = kept_value[int64_t(f) * capacity + k];
+        }
+    }
+    if (packed_peaks) {
+        const int64_t o = offsets[n_frames + 1 + f], n = offsets[n_frames + 2 + f] - o;
+        for (int64_t k = t0; k < n; k += stride) packed_peaks[o + k] = peaks[int64_t(f) * peak_capacity + k];
+    }
+}
+
 }  // namespace
 }  // namespace ss
 
@@ -1042,6 +1125,30 @@ extern "C" int ss_veto(const int64_t *n_peaks, const int64_t *n_kept, int32_t n_
     if (!n_peaks || !counters) return SS_EINVAL;
     k_veto<<<dim3(uint32_t((n_frames + kVetoBlock - 1) / kVetoBlock)), kVetoBlock, 0, stream>>>(
         n_peaks, n_kept, n_frames, threshold, hit, reinterpret_cast<unsigned long long *>(counters));
+    SS_RETURN_IF_LAUNCH_FAILED();
+    return SS_OK;
+}
+
+extern "C" int ss_pack_results(const uint32_t *kept_index, const float *kept_value, int64_t capacity,
+                               const int64_t *n_kept, const ss_peak *peaks, int64_t peak_capacity,
+                               const int64_t *n_peaks, int32_t n_frames, int64_t *offsets, uint32_t *packed_index,
+                               float *packed_value, ss_peak *packed_peaks, hipStream_t stream) {
+    using namespace ss;
+    if (n_frames < 0 || n_frames > 65535 || capacity < 0 || peak_capacity < 0) return SS_ESIZE;
+    if (!offsets) return SS_EINVAL;
+    const bool keep = kept_index || kept_value || n_kept || packed_index || packed_value;
+    const bool pk = peaks || n_peaks || packed_peaks;
+    if (keep && (!kept_index || !kept_value || !n_kept || !packed_index || !packed_value)) return SS_EINVAL;
+    if (pk && (!peaks || !n_peaks || !packed_peaks)) return SS_EINVAL;
+    k_pack_offsets<<<dim3(1), kPackBlock, 0, stream>>>(keep ? n_kept : nullptr, capacity, pk ? n_peaks : nullptr,
+                                                       peak_capacity, n_frames, offsets);
+    SS_RETURN_IF_LAUNCH_FAILED();
+    if (n_frames == 0 || (!keep && !pk)) return SS_OK;
+    const int64_t longest = max(keep ? capacity : int64_t(0), pk ? peak_capacity : int64_t(0));
+    const int64_t blocks = max(int64_t(1), min(int64_t(64), (longest + kPackBlock - 1) / kPackBlock));
+    k_pack_copy<<<dim3(uint32_t(blocks), uint32_t(n_frames)), kPackBlock, 0, stream>>>(
+        kept_index, kept_value, capacity, peaks, peak_capacity, n_frames, offsets, keep ? packed_index : nullptr,
+        keep ? packed_value : nullptr, pk ? packed_peaks : nullptr);
     SS_RETURN_IF_LAUNCH_FAILED();
     return SS_OK;
 }

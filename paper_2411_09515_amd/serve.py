@@ -26,6 +26,8 @@ kernels; this module only schedules them.
 from __future__ import annotations
 
 import collections
+import ctypes
+import gc
 import time
 from dataclasses import dataclass, field
 
@@ -72,7 +74,9 @@ class Detector:
     def slot_bytes(self):
         N, nb, B_ = self.geom.n_pix, self.geom.n_bins, self.max_batch
         ws = api.workspace_bytes(B_, N, nb)
-        per = N * (2 + 4) + nb * (4 * 8 + 3 * 4) + self.kept_capacity * 8 + self.peak_capacity * B.PEAK_BYTES + 16
+        # raw + frames, profile, results and their packed copies, counts
+        per = (N * (2 + 4) + nb * (4 * 8 + 3 * 4) + 2 * (self.kept_capacity * 8 + self.peak_capacity * B.PEAK_BYTES)
+               + 32)
         return B_ * per + ws
 
 
@@ -91,25 +95,77 @@ class _Slot:
                         peaks=torch.empty((F, det.peak_capacity, B.PEAK_BYTES), dtype=torch.uint8,
                                           device=device),
                         n_peaks=torch.empty(F, dtype=torch.int64, device=device))
+        # every frame's results packed back to back (one copy per kind to the host)
+        self.packed = dict(offsets=torch.empty(2 * (F + 1), dtype=torch.int64, device=device),
+                           index=torch.empty(F * det.kept_capacity, dtype=torch.int32, device=device),
+                           value=torch.empty(F * det.kept_capacity, dtype=torch.float32, device=device),
+                           peaks=torch.empty((F * det.peak_capacity, B.PEAK_BYTES), dtype=torch.uint8,
+                                             device=device))
         self.h_idx = torch.empty(F, dtype=torch.int64, pin_memory=True)
         self.d_idx = torch.empty(F, dtype=torch.int64, device=device)
         self.h_counts = torch.empty((2, F), dtype=torch.int64, pin_memory=True)
+        self.h_offsets = torch.empty(2 * (F + 1), dtype=torch.int64, pin_memory=True)
         self.h_mean = torch.empty((F, nb), dtype=torch.float64, pin_memory=True)
         self.h_std = torch.empty((F, nb), dtype=torch.float64, pin_memory=True)
-        self.h_kept_index = torch.empty((F, det.kept_capacity), dtype=torch.int32, pin_memory=True)
-        self.h_kept_value = torch.empty((F, det.kept_capacity), dtype=torch.float32, pin_memory=True)
-        self.h_peaks = torch.empty((F, det.peak_capacity, B.PEAK_BYTES), dtype=torch.uint8, pin_memory=True)
+        self.h_index = torch.empty(F * det.kept_capacity, dtype=torch.int32, pin_memory=True)
+        self.h_value = torch.empty(F * det.kept_capacity, dtype=torch.float32, pin_memory=True)
+        self.h_peaks = torch.empty((F * det.peak_capacity, B.PEAK_BYTES), dtype=torch.uint8, pin_memory=True)
+        # touch every page of the pinned buffers now: first touches fault, and
+        # would otherwise land inside the serving loop
+        for t in (self.h_idx, self.h_counts, self.h_offsets, self.h_mean, self.h_std, self.h_index, self.h_value,
+                  self.h_peaks):
+            t.zero_()
         self.stream = stream
+        self.graphs = {}     # batch size -> captured device work of one batch
         self.ev_counts = torch.cuda.Event()
         self.ev_done = torch.cuda.Event()
         self.batch = []
         self.phase = 0   # 0 free, 1 computing, 2 copying results
 
+    def device_work(self, F):
+        """The whole path on the first F ring frames named by d_idx, on the
+        current stream: gather, correct, clip, classify, pack."""
+        d = self.det
+        torch.index_select(d.ring, 0, self.d_idx[:F], out=self.raw[:F])
+        frames = self.frames[:F]
+        api.correct(self.raw[:F], d.pedestal, d.gain, d.geom.norm, out=frames, n_invalid=self.n_invalid[:F])
+        prof = {k: v[:F] for k, v in self.profile.items()}
+        api.sigma_clip(frames, d.geom, d.params, out=prof)
+        out = {k: v[:F] for k, v in self.out.items()}
+        api.classify(frames, d.geom, prof, d.params, d.kept_capacity, d.peak_capacity,
+                     workspace=self.workspace, out=out)
+        packed = dict(offsets=self.packed["offsets"][:2 * (F + 1)], index=self.packed["index"],
+                      value=self.packed["value"], peaks=self.packed["peaks"])
+        api.pack_results(out, d.kept_capacity, d.peak_capacity, packed)
+
+
+def _keep_result_buffers_on_the_heap():
+    """Results handed to the host are fresh arrays of a few hundred KB per
+    frame; glibc serves such sizes with a new mapping each time (every page
+    faults on first touch) until its adaptive threshold has grown, and hands
+    freed heap back to the system.  Fixing both thresholds keeps results on
+    heap pages that, once touched, stay mapped: a serving process reaches a
+    steady state without page faults on the result path."""
+    try:
+        libc = ctypes.CDLL("libc.so.6")
+    except OSError:
+        return False
+    M_TRIM_THRESHOLD, M_MMAP_THRESHOLD = -1, -3
+    ok = libc.mallopt(M_MMAP_THRESHOLD, 32 << 20) == 1
+    ok = libc.mallopt(M_TRIM_THRESHOLD, -1) == 1 and ok   # never hand freed heap back
+    return ok
+
 
 class Server:
-    """Continuous batching over detectors within an HBM budget (bytes)."""
+    """Continuous batching over detectors within an HBM budget (bytes).
 
-    def __init__(self, detectors, hbm_budget=8 << 30, device="cuda", max_slots_per_detector=4):
+    With ``tune_malloc`` (default) the process's malloc thresholds are set
+    so that per-request result arrays come from the heap (see
+    ``_keep_result_buffers_on_the_heap``)."""
+
+    def __init__(self, detectors, hbm_budget=8 << 30, device="cuda", max_slots_per_detector=4, tune_malloc=True):
+        if tune_malloc:
+            _keep_result_buffers_on_the_heap()
         self.detectors = list(detectors)
         self.device = torch.device(device)
         self.slots = []
@@ -139,54 +195,50 @@ class Server:
     # -- one batch -----------------------------------------------------------------------
 
     def _launch(self, slot: _Slot, batch):
-        d = slot.det
         F = len(batch)
         for f, r in enumerate(batch):
             slot.h_idx[f] = r.ring_index
         with torch.cuda.stream(slot.stream):
             slot.d_idx[:F].copy_(slot.h_idx[:F], non_blocking=True)
-            torch.index_select(d.ring, 0, slot.d_idx[:F], out=slot.raw[:F])
-            frames = slot.frames[:F]
-            api.correct(slot.raw[:F], d.pedestal, d.gain, d.geom.norm, out=frames, n_invalid=slot.n_invalid[:F])
-            prof = {k: v[:F] for k, v in slot.profile.items()}
-            api.sigma_clip(frames, d.geom, d.params, out=prof)
-            out = {k: v[:F] for k, v in slot.out.items()}
-            api.classify(frames, d.geom, prof, d.params, d.kept_capacity, d.peak_capacity,
-                         workspace=slot.workspace, out=out)
-            slot.h_counts[0, :F].copy_(out["n_kept"], non_blocking=True)
-            slot.h_counts[1, :F].copy_(out["n_peaks"], non_blocking=True)
-            slot.h_mean[:F].copy_(prof["mean"], non_blocking=True)
-            slot.h_std[:F].copy_(prof["std"], non_blocking=True)
+            g = slot.graphs.get(F)
+            if g is not None:
+                g.replay()
+            else:
+                slot.device_work(F)
+            slot.h_offsets[:2 * (F + 1)].copy_(slot.packed["offsets"][:2 * (F + 1)], non_blocking=True)
+            slot.h_counts[0, :F].copy_(slot.out["n_kept"][:F], non_blocking=True)
+            slot.h_counts[1, :F].copy_(slot.out["n_peaks"][:F], non_blocking=True)
+            slot.h_mean[:F].copy_(slot.profile["mean"][:F], non_blocking=True)
+            slot.h_std[:F].copy_(slot.profile["std"][:F], non_blocking=True)
             slot.ev_counts.record(slot.stream)
         slot.batch = batch
         slot.phase = 1
 
     def _fetch(self, slot: _Slot):
-        d = slot.det
         F = len(slot.batch)
-        nk = np.minimum(slot.h_counts[0, :F].numpy(), d.kept_capacity)
-        npk = np.minimum(slot.h_counts[1, :F].numpy(), d.peak_capacity)
+        tk = int(slot.h_offsets[F])
+        tp = int(slot.h_offsets[2 * F + 1])
         with torch.cuda.stream(slot.stream):
-            # contiguous row prefixes only: those copies stay asynchronous
-            for f in range(F):
-                if nk[f]:
-                    slot.h_kept_index[f, :nk[f]].copy_(slot.out["kept_index"][f, :nk[f]], non_blocking=True)
-                    slot.h_kept_value[f, :nk[f]].copy_(slot.out["kept_value"][f, :nk[f]], non_blocking=True)
-                if npk[f]:
-                    slot.h_peaks[f, :npk[f]].copy_(slot.out["peaks"][f, :npk[f]], non_blocking=True)
+            # exactly the packed results: one contiguous copy per kind
+            if tk:
+                slot.h_index[:tk].copy_(slot.packed["index"][:tk], non_blocking=True)
+                slot.h_value[:tk].copy_(slot.packed["value"][:tk], non_blocking=True)
+            if tp:
+                slot.h_peaks[:tp].copy_(slot.packed["peaks"][:tp], non_blocking=True)
             slot.ev_done.record(slot.stream)
         slot.phase = 2
 
     def _finish(self, slot: _Slot, now):
         F = len(slot.batch)
         counts = slot.h_counts[:, :F].numpy()
+        off = slot.h_offsets[:2 * (F + 1)].numpy()
         for f, r in enumerate(slot.batch):
-            nk = min(int(counts[0, f]), slot.det.kept_capacity)
-            npk = min(int(counts[1, f]), slot.det.peak_capacity)
+            k0, k1 = int(off[f]), int(off[f + 1])
+            p0, p1 = int(off[F + 1 + f]), int(off[F + 2 + f])
             r.n_kept, r.n_peaks = int(counts[0, f]), int(counts[1, f])
-            r.kept_index = slot.h_kept_index[f, :nk].numpy().view(np.uint32).copy()
-            r.kept_value = slot.h_kept_value[f, :nk].numpy().copy()
-            r.peaks = api.peaks_to_numpy(slot.h_peaks[f], npk)
+            r.kept_index = slot.h_index[k0:k1].numpy().view(np.uint32).copy()
+            r.kept_value = slot.h_value[k0:k1].numpy().copy()
+            r.peaks = api.peaks_to_numpy(slot.h_peaks[p0:p1], p1 - p0)
             r.mean = slot.h_mean[f].numpy().copy()
             r.std = slot.h_std[f].numpy().copy()
             r.batch_size = F
@@ -194,9 +246,44 @@ class Server:
         slot.batch = []
         slot.phase = 0
 
-    def warmup(self):
-        """One batch of one frame and one full batch per detector, so that the
-        first served frames do not pay for loading kernels."""
+    def capture_graphs(self):
+        """Capture every slot's device work for every batch size as a HIP
+        graph (one launch per batch instead of one per kernel).  The graphs
+        hold no copies to the host and no memory sets."""
+        torch.cuda.synchronize(self.device)
+        # no garbage collection while capturing: collecting an unreachable
+        # graph of another object would destroy it in the middle of a capture
+        gc.collect()
+        was_enabled = gc.isenabled()
+        gc.disable()
+        try:
+            for s in self.slots:
+                for F in range(1, s.det.max_batch + 1):
+                    s.d_idx[:F].zero_()
+                    with torch.cuda.stream(s.stream):
+                        s.device_work(F)          # eager run first: nothing is initialised inside the capture
+                    s.stream.synchronize()
+                    g = torch.cuda.CUDAGraph()
+                    with torch.cuda.graph(g, stream=s.stream):
+                        s.device_work(F)
+                    s.graphs[F] = g
+        finally:
+            if was_enabled:
+                gc.enable()
+        torch.cuda.synchronize(self.device)
+
+    def close(self):
+        """Release the captured graphs (before the device buffers they use)."""
+        torch.cuda.synchronize(self.device)
+        for s in self.slots:
+            s.graphs.clear()
+
+    def warmup(self, graphs=True):
+        """Graphs for every slot and batch size (unless ``graphs`` is False),
+        then one batch of one frame and one full batch per detector, so that
+        the first served frames pay for neither capture nor kernel loading."""
+        if graphs:
+            self.capture_graphs()
         reqs = []
         for d_i, d in enumerate(self.detectors):
             reqs.append(Request(det=d_i, ring_index=0, t_arrival=0.0))

@@ -67,12 +67,50 @@ def test_results_are_the_same_alone_and_in_the_mix(dev, detectors):
             (r,), _ = server.run([serve.Request(det=d, ring_index=k, t_arrival=0.0)], realtime=False)
             assert r.batch_size == 1
             alone[(d, k)] = r
-    _say("case: mixed Poisson arrivals, 2000 Hz aggregate, 0.25 s")
-    reqs = serve.poisson_arrivals([900, 600, 300, 200], 0.25, [RING] * len(detectors), seed=5)
-    done, stats = server.run(reqs, realtime=True)
-    _say(stats)
-    assert stats["frames"] == len(reqs) and all(np.isfinite(r.t_done) for r in done)
-    assert stats["max_batches_in_flight"] >= 2          # batches overlap on the device
-    assert max(r.batch_size for r in done) >= 2         # frames that waited were batched
-    for r in done:
-        _same(r, alone[(r.det, r.ring_index)], (r.rid, r.det, r.ring_index, r.batch_size))
+    for mode in ("eager launches", "graph replays"):
+        if mode == "graph replays":
+            _say("case: capture every slot's batch sizes as graphs")
+            server.capture_graphs()
+            assert all(len(s.graphs) == s.det.max_batch for s in server.slots)
+            for d in range(len(detectors)):   # a graph of one frame gives the eager result bit for bit
+                (r,), _ = server.run([serve.Request(det=d, ring_index=1, t_arrival=0.0)], realtime=False)
+                a = alone[(d, 1)]
+                assert np.array_equal(r.mean, a.mean) and np.array_equal(r.std, a.std)
+                _same(r, a, ("graph alone", d))
+        _say(f"case: mixed Poisson arrivals, 2000 Hz aggregate, 0.25 s, {mode}")
+        reqs = serve.poisson_arrivals([900, 600, 300, 200], 0.25, [RING] * len(detectors), seed=5)
+        done, stats = server.run(reqs, realtime=True)
+        _say(stats)
+        assert stats["frames"] == len(reqs) and all(np.isfinite(r.t_done) for r in done)
+        assert stats["max_batches_in_flight"] >= 2          # batches overlap on the device
+        assert max(r.batch_size for r in done) >= 2         # frames that waited were batched
+        for r in done:
+            _same(r, alone[(r.det, r.ring_index)], (mode, r.rid, r.det, r.ring_index, r.batch_size))
+
+
+def test_packed_results_match_the_per_frame_layout(dev):
+    """ss_pack_results: every frame's kept entries and peaks back to back,
+    counts clamped to the capacities (one frame overflows its capacity)."""
+    g = synth.SMALL
+    _say("case: pack results, small-512 x5")
+    geo = api.Geometry.from_scene(g, synth.stripe_mask(g), None, dev)
+    fr = torch.from_numpy(synth.float_frames(g, 5).reshape(5, -1)).to(dev)
+    p = api.Params(n_pick=1.5)
+    prof = api.sigma_clip(fr, geo, p)
+    out = api.classify(fr, geo, prof, p, capacity=20000, peak_capacity=10)
+    packed = api.pack_results(out, 20000, 10)
+    torch.cuda.synchronize()
+    nk = out["n_kept"].cpu().numpy()
+    npk = out["n_peaks"].cpu().numpy()
+    assert nk.max() > 0 and npk.max() > 10          # more peaks than room
+    ck, cp = np.minimum(nk, 20000), np.minimum(npk, 10)
+    off = packed["offsets"].cpu().numpy()
+    assert np.array_equal(off[:6], np.concatenate([[0], np.cumsum(ck)]))
+    assert np.array_equal(off[6:], np.concatenate([[0], np.cumsum(cp)]))
+    for f in range(5):
+        assert torch.equal(packed["index"][off[f]:off[f + 1]], out["kept_index"][f, :ck[f]])
+        assert torch.equal(packed["value"][off[f]:off[f + 1]], out["kept_value"][f, :ck[f]])
+        assert torch.equal(packed["peaks"][off[6 + f]:off[7 + f]], out["peaks"][f, :cp[f]])
+    # peaks only
+    only = api.pack_results({k: out[k] for k in ("peaks", "n_peaks")}, 20000, 10)
+    assert torch.equal(only["offsets"][6:], packed["offsets"][6:]) and int(only["offsets"][5]) == 0
