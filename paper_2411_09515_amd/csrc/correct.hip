@@ -22,7 +22,10 @@ __global__ void k_fill_i64(int64_t *p, int64_t n, int64_t value) {
 namespace {
 
 constexpr int kVec = 4;
-constexpr int kCorrectBlock = 256;
+#ifndef SS_CORRECT_BLOCK
+#define SS_CORRECT_BLOCK 256
+#endif
+constexpr int kCorrectBlock = SS_CORRECT_BLOCK;
 
 // float32(a / b) rounded to nearest, for a and b exact in float64, given
 // r = float64(1 / b).  The product a * r lies within |q| * 2^-51 of a / b, so
@@ -76,7 +79,10 @@ __device__ inline float correct_one(uint32_t word, int64_t i, const PixelCal &c,
     return norm ? div_round32(double(s), norm + i, c.rnorm) : s;
 }
 
-constexpr int kFrameUnroll = 4;
+#ifndef SS_CORRECT_UNROLL
+#define SS_CORRECT_UNROLL 4
+#endif
+constexpr int kFrameUnroll = SS_CORRECT_UNROLL;
 
 // Vector path: n_pix % 4 == 0 and 8/16-byte aligned buffers.
 __global__ __launch_bounds__(kCorrectBlock) void k_correct_vec(

@@ -168,3 +168,42 @@ def test_schedule_groups_rows_by_class():
     good = B.Params(3.0, 5, 0, 0.0, 3.0, 0.0, 3.0, 3, 3)
     ref = ctypes.byref
     assert L.ss_sigma_clip(ctypes.c_void_p(4096), None, None, 1, ref(bad), ref(good), ref(prof), None) == B.SS_EINVAL
+
+
+def test_densify_veto_and_pack_reject_bad_arguments_before_launch():
+    """Host-side validation of the densification, veto and packing entry
+    points (nothing reaches the HIP runtime)."""
+    L = B.lib()
+    fake = ctypes.c_void_p(4096)
+    ref = ctypes.byref
+    rad = B.Radial(10, 0.05, 0.1, 4096)
+    prof = B.Profile(*([4096] * 7))
+    need = L.ss_densify_workspace(2, 10)
+    assert need > 0 and L.ss_densify_workspace(-1, 10) == 0
+    noise = B.Noise(7, 0, 3.0)
+    nan_noise = B.Noise(7, 0, float("nan"))
+    assert L.ss_densify(fake, fake, 8, fake, None, 2, 100, None, ref(prof), None, fake, fake, need,
+                        None) == B.SS_EINVAL
+    assert L.ss_densify(fake, fake, 8, fake, None, -1, 100, ref(rad), ref(prof), None, fake, fake, need,
+                        None) == B.SS_ESIZE
+    assert L.ss_densify(fake, fake, 8, fake, None, 0, 100, ref(rad), ref(prof), None, fake, fake, need,
+                        None) == B.SS_OK
+    assert L.ss_densify(fake, fake, 8, fake, None, 2, 100, ref(rad), ref(prof), ref(nan_noise), fake, fake, need,
+                        None) == B.SS_EINVAL
+    assert L.ss_densify(None, fake, 8, fake, None, 2, 100, ref(rad), ref(prof), ref(noise), fake, fake, need,
+                        None) == B.SS_EINVAL
+    assert L.ss_densify(fake, fake, 8, fake, None, 2, 100, ref(rad), ref(prof), None, None, fake, need,
+                        None) == B.SS_EINVAL
+    assert L.ss_densify(fake, fake, 8, fake, None, 2, 100, ref(rad), ref(prof), None, fake, fake, need - 1,
+                        None) == B.SS_ESIZE
+    big = B.Radial(B.SS_MAX_BINS + 1, 0.05, 0.1, 4096)
+    assert L.ss_densify(fake, fake, 8, fake, None, 2, 100, ref(big), ref(prof), None, fake, fake, need,
+                        None) == B.SS_ESIZE
+    assert L.ss_veto(fake, fake, -1, 20, fake, fake, None) == B.SS_ESIZE
+    assert L.ss_veto(fake, fake, 0, 20, fake, fake, None) == B.SS_OK
+    assert L.ss_veto(None, fake, 4, 20, fake, fake, None) == B.SS_EINVAL
+    assert L.ss_veto(fake, fake, 4, 20, fake, None, None) == B.SS_EINVAL
+    assert L.ss_pack_results(fake, fake, 8, fake, fake, 4, fake, -1, fake, fake, fake, fake, None) == B.SS_ESIZE
+    assert L.ss_pack_results(fake, fake, 8, fake, fake, 4, fake, 2, None, fake, fake, fake, None) == B.SS_EINVAL
+    assert L.ss_pack_results(fake, fake, 8, fake, None, 4, fake, 2, fake, fake, fake, fake, None) == B.SS_EINVAL
+    assert L.ss_pack_results(fake, None, 8, fake, None, 4, None, 2, fake, fake, fake, None, None) == B.SS_EINVAL
