@@ -231,12 +231,12 @@ int ss_correct(const uint16_t *raw, int32_t n_frames, int64_t n_pix,
                float *out, int64_t *n_invalid, hipStream_t stream);
 
 /*
- * ss_integrate -- azimuthal average with uncertainties (Sec. 2.2, eqs. avg
+ * ss_integrate_csr -- azimuthal average with uncertainties (Sec. 2.2, eqs. avg
  * to sem2), no clipping: ss_sigma_clip with max_iter forced to 0.
  */
-int ss_integrate(const float *frames, const float *norm, const uint8_t *mask,
-                 int32_t n_frames, const ss_csr *csr, const ss_params *params,
-                 const ss_profile *out, hipStream_t stream);
+int ss_integrate_csr(const float *frames, const float *norm, const uint8_t *mask,
+                     int32_t n_frames, const ss_csr *csr, const ss_params *params,
+                     const ss_profile *out, hipStream_t stream);
 
 /* One batch of frames with its own geometry, for ss_sigma_clip_batches. */
 typedef struct {

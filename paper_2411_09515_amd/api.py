@@ -176,7 +176,7 @@ def sigma_clip(frames, geom: Geometry, params: Params, out=None, norm=None, mask
         out = new_profile(F, geom.n_bins, frames.device)
     if norm is None and params.error_model != "azimuthal":
         norm = geom.norm
-    fn = B.lib().ss_integrate if integrate_only else B.lib().ss_sigma_clip
+    fn = B.lib().ss_integrate_csr if integrate_only else B.lib().ss_sigma_clip
     B.check("ss_sigma_clip", fn(_p(frames), _p(norm), _p(mask), F, ctypes.byref(geom.csr()),
                                 ctypes.byref(params.c()), ctypes.byref(profile_c(out)), _stream()))
     return out

@@ -35,7 +35,7 @@ SS_VETO_COUNTERS = 4 + 2 * SS_VETO_BINS
 EXPORTED = (
     "ss_strerror", "ss_version", "ss_build_csr", "ss_csr_schedule", "ss_class_rows", "ss_radial_coords",
     "ss_correct",
-    "ss_integrate", "ss_sigma_clip", "ss_classify_workspace", "ss_classify",
+    "ss_integrate_csr", "ss_sigma_clip", "ss_classify_workspace", "ss_classify",
     "ss_compress", "ss_peakfind",
     "ss_clip_features", "ss_surrogate_targets", "ss_mlp_forward", "ss_mlp_grad_workspace", "ss_mlp_grad",
     "ss_mlp_adam", "ss_sigma_clip_surrogate", "ss_sigma_clip_batches",
@@ -116,7 +116,7 @@ def lib():
         L.ss_radial_coords.argtypes = [i32, i32, f64, f64, f64, f64, i32, f64, vp, vp, P(f64), P(f64)]
         L.ss_correct.restype = ctypes.c_int
         L.ss_correct.argtypes = [vp, i32, i64, vp, vp, vp, vp, vp, vp]
-        for name in ("ss_integrate", "ss_sigma_clip"):
+        for name in ("ss_integrate_csr", "ss_sigma_clip"):
             fn = getattr(L, name)
             fn.restype = ctypes.c_int
             fn.argtypes = [vp, vp, vp, i32, P(Csr), P(Params), P(Profile), vp]

@@ -1333,9 +1333,9 @@ extern "C" int ss_sigma_clip(const float *frames, const float *norm, const uint8
     return clip_entry(frames, norm, mask, n_frames, csr, params, out, false, SurrogateIo{}, stream);
 }
 
-extern "C" int ss_integrate(const float *frames, const float *norm, const uint8_t *mask,
-                            int32_t n_frames, const ss_csr *csr, const ss_params *params,
-                            const ss_profile *out, hipStream_t stream) {
+extern "C" int ss_integrate_csr(const float *frames, const float *norm, const uint8_t *mask,
+                                int32_t n_frames, const ss_csr *csr, const ss_params *params,
+                                const ss_profile *out, hipStream_t stream) {
     return clip_entry(frames, norm, mask, n_frames, csr, params, out, true, SurrogateIo{}, stream);
 }
 

@@ -124,7 +124,7 @@ def test_device_calls_reject_bad_arguments_before_launch():
     big = B.Csr(B.SS_MAX_BINS + 1, 5, 100, 50, 4096, 4096, 4096, None)
     assert L.ss_sigma_clip(fake, None, None, 1, ref(big), ref(good), ref(prof), None) == B.SS_ESIZE
     # integrate ignores max_iter
-    assert L.ss_integrate(fake, None, None, 0, ref(csr), ref(bad_iter), ref(prof), None) == B.SS_OK
+    assert L.ss_integrate_csr(fake, None, None, 0, ref(csr), ref(bad_iter), ref(prof), None) == B.SS_OK
 
     rad = B.Radial(10, 0.05, 0.1, 4096)
     need = L.ss_classify_workspace(2, 100, 10)

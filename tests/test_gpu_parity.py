@@ -12,6 +12,7 @@ import torch
 
 import synth
 from oracle import correct as OC
+from oracle import stats as OS
 from paper_2411_09515_amd import api
 from paper_2411_09515_amd import binding as B
 
@@ -133,6 +134,21 @@ def test_clip_variants(dev, small, variant):
     prof = api.sigma_clip(torch.from_numpy(frames[:2]).to(dev), geo, p)
     for f in range(2):
         compare_profile(_prof_host(prof, f), sc.profile(frames[f], p), f"{variant} frame {f}")
+
+
+@pytest.mark.parametrize("model", ["azimuthal", "poisson", "hybrid"])
+def test_integrate_csr_matches_oracle(dev, small, model):
+    """ss_integrate_csr: the unclipped moments, whatever max_iter says."""
+    g, sc, geo, frames = small
+    p = api.Params(error_model=model, max_iter=7)
+    _say("case: integrate_csr", model)
+    prof = api.integrate(torch.from_numpy(frames[:3]).to(dev), geo, p)
+    for f in range(3):
+        ref = OS.integrate(frames[f], None, sc.csr, sc.mask, error_model={"azimuthal": 0, "poisson": 1,
+                                                                         "hybrid": 2}[model])
+        ref["margin"] = np.full(sc.csr.n_bins, np.inf)
+        compare_profile(_prof_host(prof, f), ref, f"integrate {model} frame {f}")
+        assert np.all(_prof_host(prof, f)["n_iter"] == 0)
 
 
 def test_clip_extra_mask_and_long_rows(dev, small):
