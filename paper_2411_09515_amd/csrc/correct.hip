@@ -32,51 +32,59 @@ constexpr int kCorrectBlock = SS_CORRECT_BLOCK;
 // when q - d and q + d (d = |q| * 2^-50) round to the same float32, a / b
 // rounds to it too; otherwise (a / b within 2^-50 of a float32 rounding
 // boundary, about one value in 10^8) the exact quotient is formed.
-__device__ inline float div_round32(double a, const float *b, double r) {
+__device__ inline float div_round32(double a, float b, double r) {
     const double q = a * r;
     const double d = fabs(q) * 0x1p-50;
     const float lo = float(q - d);
     const float hi = float(q + d);
-    return lo == hi ? lo : float(a / double(*b));
+    return lo == hi ? lo : float(a / double(b));
 }
 
-// Calibration of one pixel held in registers for the whole batch.
+// Calibration of one pixel held in registers for the whole batch: the three
+// pedestals and gains and the reciprocals of the gains and of the norm, so
+// that every gain level takes the certified reciprocal product (the level
+// of a word costs selects, not a divergent division).  Scalar fields keep
+// it in registers.
 struct PixelCal {
-    float ped[3];
-    float gain12[2];  // gains of levels 1 and 2 (exact division, rare)
-    double rgain0;    // 1 / gain of level 0
-    double rnorm;     // 1 / norm
+    float p0, p1, p2;
+    float g0, g1, g2;
+    double r0, r1, r2;  // 1 / gain of levels 0, 1, 2
+    float norm;
+    double rnorm;       // 1 / norm
 };
 
 __device__ inline PixelCal load_cal(const float *__restrict__ ped, const float *__restrict__ gain,
                                     const float *__restrict__ norm, int64_t i, int64_t n_pix) {
     PixelCal c;
-    c.ped[0] = ped[i];
-    c.ped[1] = ped[n_pix + i];
-    c.ped[2] = ped[2 * n_pix + i];
-    c.gain12[0] = gain[n_pix + i];
-    c.gain12[1] = gain[2 * n_pix + i];
-    c.rgain0 = 1.0 / double(gain[i]);
-    c.rnorm = norm ? 1.0 / double(norm[i]) : 1.0;
+    c.p0 = ped[i];
+    c.p1 = ped[n_pix + i];
+    c.p2 = ped[2 * n_pix + i];
+    c.g0 = gain[i];
+    c.g1 = gain[n_pix + i];
+    c.g2 = gain[2 * n_pix + i];
+    c.r0 = 1.0 / double(c.g0);
+    c.r1 = 1.0 / double(c.g1);
+    c.r2 = 1.0 / double(c.g2);
+    c.norm = norm ? norm[i] : 1.0f;
+    c.rnorm = 1.0 / double(c.norm);
     return c;
 }
 
 // Corrected intensity of one raw word: f32(f32((adc - ped) / gain) / norm).
-__device__ inline float correct_one(uint32_t word, int64_t i, const PixelCal &c, const float *__restrict__ gain,
-                                    const float *__restrict__ norm, int &invalid) {
+// Gain codes 0, 1 and 3 select levels 0, 1 and 2; code 2 is invalid (NaN,
+// counted).  Branch free apart from the rare exact division.
+__device__ inline float correct_one(uint32_t word, const PixelCal c, bool has_norm, int &invalid) {
     const uint32_t code = (word >> 14) & 3u;
+    const bool bad = code == 2u;
+    const bool l0 = code == 0u, l1 = code == 1u;
     const double adc = double(word & 0x3FFFu);
-    float s;
-    if (code == 0u) {
-        s = div_round32(adc - double(c.ped[0]), gain + i, c.rgain0);
-    } else if (code == 2u) {
-        invalid += 1;
-        return __builtin_nanf("");
-    } else {
-        const int g = code == 1u ? 1 : 2;
-        s = float((adc - double(c.ped[g])) / double(c.gain12[g - 1]));
-    }
-    return norm ? div_round32(double(s), norm + i, c.rnorm) : s;
+    const float pg = l0 ? c.p0 : (l1 ? c.p1 : c.p2);
+    const float gg = l0 ? c.g0 : (l1 ? c.g1 : c.g2);
+    const double rg = l0 ? c.r0 : (l1 ? c.r1 : c.r2);
+    const float s = div_round32(adc - double(pg), gg, rg);
+    const float v = has_norm ? div_round32(double(s), c.norm, c.rnorm) : s;
+    invalid += bad ? 1 : 0;
+    return bad ? __builtin_nanf("") : v;
 }
 
 #ifndef SS_CORRECT_UNROLL
@@ -109,7 +117,7 @@ __global__ __launch_bounds__(kCorrectBlock) void k_correct_vec(
             int invalid = 0;
             float o[kVec];
 #pragma unroll
-            for (int k = 0; k < kVec; ++k) o[k] = correct_one(words[k], p0 + k, cal[k], gain, norm, invalid);
+            for (int k = 0; k < kVec; ++k) o[k] = correct_one(words[k], cal[k], norm != nullptr, invalid);
             *reinterpret_cast<float4 *>(out + int64_t(f) * n_pix + p0) = make_float4(o[0], o[1], o[2], o[3]);
             if (invalid && n_invalid)
                 atomicAdd(reinterpret_cast<unsigned long long *>(n_invalid + f), (unsigned long long)invalid);
@@ -128,7 +136,7 @@ __global__ __launch_bounds__(kCorrectBlock) void k_correct_scalar(
     for (int f = 0; f < n_frames; ++f) {
         const int64_t at = int64_t(f) * n_pix + i;
         int invalid = 0;
-        out[at] = correct_one(raw[at], i, cal, gain, norm, invalid);
+        out[at] = correct_one(raw[at], cal, norm != nullptr, invalid);
         if (invalid && n_invalid) atomicAdd(reinterpret_cast<unsigned long long *>(n_invalid + f),
                                             (unsigned long long)invalid);
     }
