@@ -651,25 +651,39 @@ __global__ __launch_bounds__(kBlock) void k_tile_write(ClassArgs a) {
     const int64_t p0 = int64_t(tile) * kTile + int64_t(kPPT) * threadIdx.x;
     const float *__restrict__ fr = a.frames + int64_t(f) * a.n_pix;
     const uint8_t *__restrict__ bits = a.ws.bits + int64_t(f) * a.n_pix;
+    // the tile's offsets do not depend on the scan below: load them first
+    const uint64_t toff = a.ws.offsets[int64_t(f) * a.tiles + tile];
     uint32_t kmask, pmask;
     tile_masks<KEEP, PEAKS>(bits, a.n_pix, p0, kmask, pmask);
     const uint32_t mine = uint32_t(__popc(kmask)) | (uint32_t(__popc(pmask)) << 16);
     uint32_t total;
     const uint32_t before = block_exclusive_scan(mine, wave_tot, total);
     if (total == 0) return;
-    const uint64_t toff = a.ws.offsets[int64_t(f) * a.tiles + tile];
     int64_t pos_k = int64_t(toff & 0xFFFFFFFFu) + (before & 0xFFFFu);
     int64_t pos_p = int64_t(toff >> 32) + (before >> 16);
     if (KEEP) {
+        // kept pixels four at a time: their values are loaded together, then stored
+        constexpr int kBatch = 4;
         uint32_t m = kmask;
         while (m) {
-            const int k = __builtin_ctz(m);
-            m &= m - 1;
-            if (pos_k < a.capacity) {
-                a.kept_index[int64_t(f) * a.capacity + pos_k] = uint32_t(p0 + k);
-                a.kept_value[int64_t(f) * a.capacity + pos_k] = fr[p0 + k];
+            int ks[kBatch];
+            float vs[kBatch];
+#pragma unroll
+            for (int u = 0; u < kBatch; ++u) {
+                ks[u] = m ? __builtin_ctz(m) : -1;
+                m &= m ? m - 1 : 0u;
             }
-            ++pos_k;
+#pragma unroll
+            for (int u = 0; u < kBatch; ++u) vs[u] = ks[u] >= 0 ? fr[p0 + ks[u]] : 0.0f;
+#pragma unroll
+            for (int u = 0; u < kBatch; ++u) {
+                if (ks[u] < 0) break;
+                if (pos_k < a.capacity) {
+                    a.kept_index[int64_t(f) * a.capacity + pos_k] = uint32_t(p0 + ks[u]);
+                    a.kept_value[int64_t(f) * a.capacity + pos_k] = vs[u];
+                }
+                ++pos_k;
+            }
         }
     }
     if (PEAKS && pmask) {
