@@ -483,6 +483,21 @@ def main():
     if lat:
         latency = {"p50": round(float(np.percentile(lat, 50)), 4), "p99": round(float(np.percentile(lat, 99)), 4),
                    "frames": len(lat)}
+        # the same path captured once as a HIP graph, the frame written into its input buffer
+        buf = raw[:1].clone()
+        one.capture(buf)
+        lat_g = []
+        for i in range(args.latency_iters + 5):
+            buf.copy_(raw[i % F: i % F + 1])
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            one.replay()
+            b.record(stream)
+            b.synchronize()
+            if i >= 5:
+                lat_g.append(a.elapsed_time(b))
+        latency["graph_p50"] = round(float(np.percentile(lat_g, 50)), 4)
+        latency["graph_p99"] = round(float(np.percentile(lat_g, 99)), 4)
 
     sur = None
     if train_np is not None:

@@ -4,6 +4,7 @@ PyTorch, every step of the path runs in the library's HIP kernels."""
 from __future__ import annotations
 
 import ctypes
+import gc
 from dataclasses import dataclass
 
 import numpy as np
@@ -549,4 +550,31 @@ class Pipeline:
             frames = self.frames
         self.separate(frames)
         self.classify(frames)
+        return self.out
+
+    def capture(self, raw):
+        """Capture one pass over the raw frames in ``raw`` (a fixed device
+        buffer the caller refills) as a HIP graph; ``replay`` then runs the
+        whole path with one launch.  The graph holds no memory sets."""
+        gc.collect()
+        was_enabled = gc.isenabled()
+        gc.disable()
+        try:
+            side = torch.cuda.Stream(device=raw.device)
+            side.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(side):
+                self.run(raw)                   # eager first: nothing initialised inside the capture
+            torch.cuda.current_stream().wait_stream(side)
+            torch.cuda.synchronize(raw.device)
+            self.graph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(self.graph, stream=side):
+                self.run(raw)
+        finally:
+            if was_enabled:
+                gc.enable()
+        return self.graph
+
+    def replay(self):
+        """The captured pass, on the current stream; returns the output tensors."""
+        self.graph.replay()
         return self.out

@@ -83,3 +83,33 @@ def test_repeated_frames_are_identical(dev, batch):
             assert torch.equal(out["kept_index"][f, :n], out["kept_index"][r, :n])
             assert torch.equal(out["kept_value"][f, :n], out["kept_value"][r, :n])
             assert torch.equal(out["peaks"][f, :m], out["peaks"][r, :m])
+
+
+def test_single_frame_graph_replays_match_eager(dev, batch):
+    """The single-frame path captured once as a HIP graph: each replay, on a
+    new frame written into its input buffer, equals the eager call bit for
+    bit (eager work runs between the replays)."""
+    g, sc, raw, pipe, out, p = batch
+    _say("case: single-frame graph replays vs eager")
+    one = api.Pipeline(pipe.geom, p, 1, pipe.pedestal, pipe.gain, kept_capacity=1 << 16, peak_capacity=1 << 12,
+                       device=dev)
+    ref = api.Pipeline(pipe.geom, p, 1, pipe.pedestal, pipe.gain, kept_capacity=1 << 16, peak_capacity=1 << 12,
+                       device=dev)
+    buf = torch.from_numpy(raw[:1].copy()).to(dev)
+    one.capture(buf)
+    for f in (3, 17, 3, 40):
+        buf.copy_(torch.from_numpy(raw[f:f + 1]).to(dev))
+        one.profile["mean"].fill_(-1.0)       # eager work between replays
+        one.out["n_kept"].fill_(-1)
+        torch.cuda.synchronize()
+        got = one.replay()
+        want = ref.run(torch.from_numpy(raw[f:f + 1]).to(dev))
+        torch.cuda.synchronize()
+        assert torch.equal(one.frames, ref.frames), f
+        for k in one.profile:
+            assert torch.equal(one.profile[k], ref.profile[k]), (f, k)
+        n, m = int(want["n_kept"][0]), int(want["n_peaks"][0])
+        assert int(got["n_kept"][0]) == n and int(got["n_peaks"][0]) == m, f
+        assert torch.equal(got["kept_index"][0, :n], want["kept_index"][0, :n])
+        assert torch.equal(got["kept_value"][0, :n], want["kept_value"][0, :n])
+        assert torch.equal(got["peaks"][0, :m], want["peaks"][0, :m])
