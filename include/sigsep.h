@@ -26,6 +26,12 @@
  * - Statistics are accumulated in float64; frames are float32.
  * - Calls on different streams are independent; calls that share output or
  *   workspace buffers must be ordered by the caller.
+ * - ss_sigma_clip / ss_integrate_csr on one or two frames spread their
+ *   row-length classes over three side streams that fork from and join back
+ *   to `stream` through events (so the call still completes in `stream`
+ *   order, and can be captured in a graph).  The side streams and their
+ *   events are created once per device, on first use, and kept until the
+ *   process ends; that is the library's only state.
  */
 #ifndef SIGSEP_H
 #define SIGSEP_H

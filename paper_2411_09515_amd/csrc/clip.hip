@@ -25,6 +25,7 @@
 #include <hip/hip_fp16.h>
 
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "common.h"
@@ -1182,6 +1183,43 @@ int class_of(int32_t rows) {
 // kernels sized to the class); otherwise one launch sized to the longest
 // row.  The Poisson and hybrid models and an extra mask take the streaming
 // kernel.
+// Side streams for small batches.  The row-length classes of one call are
+// independent, and with one or two frames each class launch holds too few
+// work-groups to fill the device, so their launches run side by side: the
+// caller's stream forks to up to kSide side streams through an event and
+// joins them through one event each (default priority; capturable in a
+// graph).  Created once per device; the enqueue sequence is serialised by a
+// mutex, and each wait takes the event's state at the time it is enqueued,
+// so the events are reused.
+constexpr int kSide = 3;
+constexpr int kSideMaxFrames = 2;
+constexpr int kMaxDevices = 64;
+
+struct SideStreams {
+    bool ok = false, failed = false;
+    hipStream_t s[kSide];
+    hipEvent_t fork, join[kSide];
+};
+
+std::mutex g_side_mu;
+SideStreams g_side[kMaxDevices];
+
+SideStreams *side_streams_locked() {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    SideStreams &ss = g_side[dev];
+    if (ss.ok) return &ss;
+    if (ss.failed) return nullptr;
+    bool good = hipEventCreateWithFlags(&ss.fork, hipEventDisableTiming) == hipSuccess;
+    for (int i = 0; i < kSide && good; ++i)
+        good = hipStreamCreateWithFlags(&ss.s[i], hipStreamNonBlocking) == hipSuccess &&
+               hipEventCreateWithFlags(&ss.join[i], hipEventDisableTiming) == hipSuccess;
+    ss.ok = good;
+    ss.failed = !good;
+    if (!good) (void)hipGetLastError();  // fall back to one stream; clear the error
+    return good ? &ss : nullptr;
+}
+
 void dispatch(ClipArgs a, const ss_csr *csr, int n_frames, int mode, hipStream_t stream) {
     const bool regs = a.model == SS_AZIMUTHAL && a.mask == nullptr && a.n_pix < (int64_t(1) << 30);
     if (!regs) {
@@ -1200,15 +1238,39 @@ void dispatch(ClipArgs a, const ss_csr *csr, int n_frames, int mode, hipStream_t
         launch_class(a, c, csr->shape[c], mode, stream);
         return;
     }
+    int classes = 0;
+    for (int c = 0; c < SS_N_CLASSES; ++c) classes += csr->class_count[c] > 0 ? 1 : 0;
+    std::unique_lock<std::mutex> lock(g_side_mu, std::defer_lock);
+    SideStreams *side = nullptr;
+    if (n_frames <= kSideMaxFrames && classes > 1) {
+        lock.lock();
+        side = side_streams_locked();
+        if (side) {
+            (void)hipEventRecord(side->fork, stream);
+            for (int i = 0; i < kSide; ++i) (void)hipStreamWaitEvent(side->s[i], side->fork, 0);
+        } else {
+            lock.unlock();
+        }
+    }
     int32_t base = 0;
+    int q = 0;
     for (int c = SS_N_CLASSES - 1; c >= 0; --c) {
         const int32_t cnt = csr->class_count[c];
         if (cnt <= 0) continue;
         a.bin_order = csr->bin_order;
         a.order_base = base;
         a.launch_bins = cnt;
-        launch_class(a, c, csr->shape[c], mode, stream);
+        // longest class on the caller's stream, the others spread over the side streams
+        const hipStream_t target = (side && q > 0) ? side->s[(q - 1) % kSide] : stream;
+        launch_class(a, c, csr->shape[c], mode, target);
         base += cnt;
+        ++q;
+    }
+    if (side) {
+        for (int i = 0; i < kSide; ++i) {
+            (void)hipEventRecord(side->join[i], side->s[i]);
+            (void)hipStreamWaitEvent(stream, side->join[i], 0);
+        }
     }
 }
 
