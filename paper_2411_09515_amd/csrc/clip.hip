@@ -540,10 +540,11 @@ __device__ __forceinline__ void clip_body(const ClipArgs &a, int g, int bin) {
     const uint32_t last = uint32_t(a.n_pix - 1);
 
     // Buffer views of the row and of the frames: every load below is issued
-    // unconditionally (slots past the row end, and frames past the batch,
-    // read 0 and are masked after) with one 32-bit offset register per slot
-    // and the slot's stride in a scalar.  A work-group waits for two memory
-    // round trips: the row's indices and weights, then the gathers.
+    // unconditionally with its whole offset in the range-checked vector
+    // offset, so slots past the row end read index 0 and weight 0 (not an
+    // entry), and frames past the batch read 0 and are masked after.  A
+    // work-group waits for two memory round trips: the row's indices and
+    // weights, then the gathers.
     const __amdgpu_buffer_rsrc_t ri = buffer_rsrc(a.indices + start, uint32_t(len) * 4u);
     const __amdgpu_buffer_rsrc_t rw = buffer_rsrc(a.weight + start, uint32_t(len) * 4u);
     __amdgpu_buffer_rsrc_t rf[FB];
@@ -555,7 +556,7 @@ __device__ __forceinline__ void clip_body(const ClipArgs &a, int g, int bin) {
     }
     const uint32_t tofs = uint32_t(tid) * 4u;
     // weight of slot e: from LDS, or again from memory for the longest rows
-#define SS_W(e) (WLDS ? w_s[(e) * BLOCK + tid] : buffer_load_f32(rw, tofs, uint32_t((e) * BLOCK) * 4u))
+#define SS_W(e) (WLDS ? w_s[(e) * BLOCK + tid] : buffer_load_f32(rw, tofs + uint32_t((e) * BLOCK) * 4u, 0u))
 
     // Values are held in pairs: float64 operands need even-aligned register
     // pairs, and single floats scattered over odd registers would leave the
@@ -564,8 +565,9 @@ __device__ __forceinline__ void clip_body(const ClipArgs &a, int g, int bin) {
     float2v vp[FB][EPT / 2];
     double K[FB];
     // sweep 1: gather, Omega, the wave's mean.  Register use peaks here, so the
-    // weights go to LDS as soon as they arrive, an entry's validity is taken
-    // into a bit mask before the gathers, and each index register is free
+    // weights go to LDS as soon as they arrive (0 for a slot that is not an
+    // entry: past the row, weight <= 0 or index outside the frame; without
+    // LDS, a bit mask holds that instead), and each index register is free
     // once its gathers are issued.
     {
         uint64_t ok_entry = 0;
@@ -573,14 +575,16 @@ __device__ __forceinline__ void clip_body(const ClipArgs &a, int g, int bin) {
             int32_t ix[EPT];
             float wt[EPT];
 #pragma unroll
-            for (int e = 0; e < EPT; ++e) wt[e] = buffer_load_f32(rw, tofs, uint32_t(e * BLOCK) * 4u);
+            for (int e = 0; e < EPT; ++e) wt[e] = buffer_load_f32(rw, tofs + uint32_t(e * BLOCK) * 4u, 0u);
 #pragma unroll
-            for (int e = 0; e < EPT; ++e) ix[e] = buffer_load_i32(ri, tofs, uint32_t(e * BLOCK) * 4u);
+            for (int e = 0; e < EPT; ++e) ix[e] = buffer_load_i32(ri, tofs + uint32_t(e * BLOCK) * 4u, 0u);
 #pragma unroll
             for (int e = 0; e < EPT; ++e) {
-                if constexpr (WLDS) w_s[e * BLOCK + tid] = wt[e];
-                const bool ok = (e * BLOCK + tid < len) && wt[e] > 0.0f && uint32_t(ix[e]) <= last;
-                ok_entry |= uint64_t(ok) << e;
+                const bool ok = wt[e] > 0.0f && uint32_t(ix[e]) <= last;
+                if constexpr (WLDS)
+                    w_s[e * BLOCK + tid] = ok ? wt[e] : 0.0f;
+                else
+                    ok_entry |= uint64_t(ok) << e;
             }
 #pragma unroll
             for (int f = 0; f < FB; ++f)
@@ -605,8 +609,8 @@ __device__ __forceinline__ void clip_body(const ClipArgs &a, int g, int bin) {
         }
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
-            const bool entry_ok = (uint32_t(ok_entry >> e) & 1u) != 0;
             const float w = SS_W(e);
+            const bool entry_ok = WLDS ? w > 0.0f : (uint32_t(ok_entry >> e) & 1u) != 0;
 #pragma unroll
             for (int f = 0; f < FB; ++f) {
                 const float x = SS_V(f, e);
@@ -787,7 +791,12 @@ __device__ __forceinline__ void clip_body(const ClipArgs &a, int g, int bin) {
 #pragma unroll
                     for (int e = 0; e < EPT; ++e) {
                         const bool out = !(SUR && ((gone[f] >> e) & 1u)) && clipped(SS_V(f, e), bnd);
-                        const uint64_t m = __builtin_amdgcn_ballot_w64(out);
+                        // the wave's mask straight from the two compares
+                        // (2 = ordered greater, 4 = ordered less; NaN never
+                        // compares), not a ballot of a materialised flag
+                        const uint64_t m = SUR ? __builtin_amdgcn_ballot_w64(out)
+                                               : (__builtin_amdgcn_fcmpf(SS_V(f, e), bnd.hi, 2) |
+                                                  __builtin_amdgcn_fcmpf(SS_V(f, e), bnd.lo, 4));
                         if (m == 0) continue;
                         const int cnt = __popcll(m);
                         if (used + cnt > kRemCap) {
