@@ -307,21 +307,25 @@ __device__ inline bool patch_is_peak(const float *v_s, const uint8_t *b_s, int e
                 nb[dy * P + dx] = b_s[q];
                 nv[dy * P + dx] = v_s[q];
             }
+        // Branch free: a neighbour that comes before the centre wins a tie,
+        // so it beats the centre when vq >= vi, any other when vq > vi (a
+        // valid pixel's value is finite); bitwise operators keep the
+        // compiler from turning the tests into short-circuit branches.
         bool best = true;
         int count = 0;
 #pragma unroll
         for (int dy = 0; dy < P; ++dy)
 #pragma unroll
             for (int dx = 0; dx < P; ++dx) {
-                const uint8_t bq = nb[dy * P + dx];
+                const uint32_t bq = nb[dy * P + dx];
                 const float vq = nv[dy * P + dx];
                 const bool centre = dy == KH && dx == KH;
                 const bool before = dy < KH || (dy == KH && dx < KH);
-                const bool valid = bq & kValid;
-                best &= !(valid && !centre && (vq > vi || (vq == vi && before)));
-                count += (valid && (bq & kCand)) ? 1 : 0;
+                const bool valid = (bq & kValid) != 0;
+                if (!centre) best = best & !(valid & (before ? vq >= vi : vq > vi));
+                count += (bq & (kValid | kCand)) == (kValid | kCand) ? 1 : 0;
             }
-        return best && count >= min_count;
+        return best & (count >= min_count);
     }
     bool best = true;
     int count = 0;

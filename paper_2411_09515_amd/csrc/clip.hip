@@ -620,6 +620,9 @@ __device__ __forceinline__ void clip_body(const ClipArgs &a, int g, int bin) {
                 // select in float32, then widen (one select per operand
                 // instead of one per half of its float64 widening)
                 asm("" : "+v"(wz), "+v"(xz));
+                // one frame per group: the LDS weight becomes the member's
+                // weight (0 for a non-member), so sweep 2 needs no select
+                if constexpr (WLDS && FB == 1) w_s[e * BLOCK + tid] = wz;
                 t[3 * f + 0] += double(wz);
                 t[3 * f + 1] = fma(double(wz), double(xz), t[3 * f + 1]);
                 n_ok[f] += ok ? 1 : 0;
@@ -662,7 +665,7 @@ __device__ __forceinline__ void clip_body(const ClipArgs &a, int g, int bin) {
             for (int f = 0; f < FB; ++f) {
                 const float x = SS_V(f, e);
                 const bool ok = x == x;
-                const double wz = double(ok ? w : 0.0f);
+                const double wz = double((WLDS && FB == 1) || ok ? w : 0.0f);
                 const double d = double(ok ? x : 0.0f) - K[f];
                 const double wd = wz * d;
                 t[4 * f + 0] += wd;
