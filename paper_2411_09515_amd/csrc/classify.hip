@@ -374,6 +374,11 @@ __global__ __launch_bounds__(kStencilBlock) void k_pixel_state(StateArgs a) {
     }
     const int f1 = min(a.n_frames, f0 + kFramesPerBlock);
     const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+    // per wave: LDS indices of its candidate core pixels (one frame at a time)
+    constexpr int kCore = kTileH * kTileW / kStencilBlock;
+    __shared__ uint16_t list_s[kStencilBlock / kWave][kCore * kWave];
+    uint16_t *list = list_s[tid / kWave];
     // e / RW as (e * magic) >> 20, exact for e < 2^20 / RW (RN is far smaller)
     const uint32_t magic = ((1u << 20) + uint32_t(RW) - 1u) / uint32_t(RW);
 
@@ -411,7 +416,6 @@ __global__ __launch_bounds__(kStencilBlock) void k_pixel_state(StateArgs a) {
     }
     // the tile's core pixels this thread tests and writes: LDS index and
     // offset in a frame (kNoPixel outside the frame)
-    constexpr int kCore = kTileH * kTileW / kStencilBlock;
     static_assert(kTileH * kTileW % kStencilBlock == 0, "whole core pixels per thread");
     constexpr uint32_t kNoPixel = 0xFFFFFFFFu;
     uint32_t soff[kCore];
@@ -483,14 +487,38 @@ __global__ __launch_bounds__(kStencilBlock) void k_pixel_state(StateArgs a) {
             for (int k = 0; k < kStageSlots; ++k) xv[k] = buffer_load_f32(rf, voff[k], 0u);
         }
         __syncthreads();
-        const __amdgpu_buffer_rsrc_t rb = buffer_rsrc(a.ws.bits + int64_t(f) * a.n_pix, uint32_t(a.n_pix));
+        // The wave's candidates (of all its core slots) are listed in LDS and
+        // take the patch test 64 at a time: a slot where one lane holds a
+        // candidate no longer costs the whole wave a test.  A lane that finds
+        // a peak sets kPeak in the pixel's LDS byte (the patch tests read
+        // only kValid and kCand of their neighbours), and the owners read
+        // their bytes back before the store.
+        uint8_t bj[kCore];
+        int n_list = 0;
 #pragma unroll
         for (int j = 0; j < kCore; ++j) {
-            const int e = cidx[j];
-            uint8_t b = b_s[e];
-            if ((b & kCand) && patch_is_peak<kH>(v_s, b_s, e, RW, h, a.min_count)) b |= kPeak;
-            if (soff[j] != kNoPixel) __builtin_amdgcn_raw_buffer_store_b8(b, rb, int(soff[j]), 0, 0);
+            bj[j] = b_s[cidx[j]];
+            const bool cand = (bj[j] & kCand) != 0;
+            const uint64_t m = __builtin_amdgcn_ballot_w64(cand);
+            if (cand) list[n_list + lanes_below(m)] = uint16_t(cidx[j]);
+            n_list += __popcll(m);
         }
+        if (n_list > 0) {
+            __builtin_amdgcn_wave_barrier();
+            for (int base = 0; base < n_list; base += kWave) {
+                if (base + lane < n_list) {
+                    const int e = list[base + lane];
+                    if (patch_is_peak<kH>(v_s, b_s, e, RW, h, a.min_count)) b_s[e] = uint8_t(b_s[e] | kPeak);
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int j = 0; j < kCore; ++j) bj[j] = b_s[cidx[j]];
+        }
+        const __amdgpu_buffer_rsrc_t rb = buffer_rsrc(a.ws.bits + int64_t(f) * a.n_pix, uint32_t(a.n_pix));
+#pragma unroll
+        for (int j = 0; j < kCore; ++j)
+            if (soff[j] != kNoPixel) __builtin_amdgcn_raw_buffer_store_b8(bj[j], rb, int(soff[j]), 0, 0);
     }
 }
 
