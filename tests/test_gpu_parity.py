@@ -343,3 +343,36 @@ def test_tiny_ragged_frame(dev):
         gp = api.peaks_to_numpy(out["peaks"][f], int(out["n_peaks"][f]))
         assert np.array_equal(gp["index"].astype(np.int64), rp["index"])
     assert int(out["n_peaks"][0]) >= 1
+
+
+@pytest.mark.parametrize("snr,patch", [(0.0, 3), (-2.0, 3), (-2.0, 5), (-2.0, 7)])
+def test_dense_candidates(dev, snr, patch):
+    """Most pixels are candidates (snr <= 0): each wave's list of candidate
+    core pixels holds well over 64 entries and takes several rounds of patch
+    tests; unrolled (3 x 3, 5 x 5) and runtime (7 x 7) patches, kept pixels
+    and peaks equal to the oracle's."""
+    _say("case: dense candidates", snr, patch)
+    H, W = 70, 150
+    rng = np.random.default_rng(31)
+    from oracle import geometry as OG
+    from oracle import classify as OKc
+    from oracle import stats as OS
+    frames = rng.poisson(40.0, (2, H * W)).astype(np.float32)
+    geo = api.Geometry(H, W, 75e-6, 0.01, 18.3, 26.1, 16, "bbox", None, None, dev)
+    csr = OG.build_csr(H, W, 75e-6, 0.01, 18.3, 26.1, 16, "bbox")
+    pos = OG.centre_angle(H, W, 75e-6, 0.01, 18.3, 26.1)
+    p = api.Params(snr=snr, patch=patch, min_count=3)
+    fr = torch.from_numpy(frames).to(dev)
+    prof = api.sigma_clip(fr, geo, p)
+    out = api.classify(fr, geo, prof, p, capacity=H * W, peak_capacity=H * W)
+    torch.cuda.synchronize()
+    for f in range(2):
+        ref = OS.sigma_clip(frames[f], None, csr, None, 3.0, 5, return_margin=True)
+        compare_profile(_prof_host(prof, f), ref, f"dense {f}")
+        ri, _ = OKc.compress(frames[f], None, pos, csr.centres, ref, 3.0)
+        n = int(out["n_kept"][f])
+        assert np.array_equal(out["kept_index"][f, :n].cpu().numpy(), ri)
+        rp = OKc.peakfind(frames[f], None, H, W, pos, csr.centres, ref, snr, patch, 3)
+        gp = api.peaks_to_numpy(out["peaks"][f], int(out["n_peaks"][f]))
+        assert np.array_equal(gp["index"].astype(np.int64), rp["index"]), (f, gp.size, rp.size)
+        assert rp.size > 10, rp.size
