@@ -163,14 +163,18 @@ class Server:
     so that per-request result arrays come from the heap (see
     ``_keep_result_buffers_on_the_heap``)."""
 
-    def __init__(self, detectors, hbm_budget=8 << 30, device="cuda", max_slots_per_detector=4, tune_malloc=True):
+    def __init__(self, detectors, hbm_budget=8 << 30, device="cuda", max_slots_per_detector=2, tune_malloc=True):
         if tune_malloc:
             _keep_result_buffers_on_the_heap()
         self.detectors = list(detectors)
         self.device = torch.device(device)
         self.slots = []
         # admission by memory: slots for each detector while the budget lasts,
-        # round robin so that every detector gets at least one
+        # round robin so that every detector gets at least one.  Two per
+        # detector by default: one batch running and one queued behind it on
+        # the detector's stream; more slots only queue more single-frame
+        # batches, while with two the frames that arrive meanwhile wait on
+        # the host and leave together in the next, larger batch.
         used = 0
         per_det = [0] * len(self.detectors)
         # one stream per detector: a detector's batches queue in order, different
