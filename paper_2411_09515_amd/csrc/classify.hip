@@ -118,25 +118,26 @@ __global__ __launch_bounds__(kTableBlock) void k_profile_table(
         hi_s[r] = run;
     }
     chunk_hi[tid] = run;
-    __syncthreads();
-    if (tid == 0) {
-        int best = -1;
-        for (int c = 0; c < kTableBlock; ++c) {
-            const int here = chunk_lo[c];
-            chunk_lo[c] = best;  // exclusive prefix max
-            if (here > best) best = here;
-        }
-        best = n_bins;
-        for (int c = kTableBlock - 1; c >= 0; --c) {
-            const int here = chunk_hi[c];
-            chunk_hi[c] = best;  // exclusive suffix min
-            if (here < best) best = here;
-        }
+    // inclusive prefix max / suffix min over the chunks, log2(kTableBlock)
+    // steps (a single frame waits for this table, so no serial scan)
+    int in_lo = chunk_lo[tid], in_hi = chunk_hi[tid];
+    for (int off = 1; off < kTableBlock; off <<= 1) {
+        __syncthreads();
+        const int plo = tid >= off ? chunk_lo[tid - off] : -1;
+        const int phi = tid + off < kTableBlock ? chunk_hi[tid + off] : n_bins;
+        __syncthreads();
+        in_lo = max(in_lo, plo);
+        in_hi = min(in_hi, phi);
+        chunk_lo[tid] = in_lo;
+        chunk_hi[tid] = in_hi;
     }
     __syncthreads();
+    // exclusive: the chunks before (after) this one
+    const int ex_lo = tid > 0 ? chunk_lo[tid - 1] : -1;
+    const int ex_hi = tid + 1 < kTableBlock ? chunk_hi[tid + 1] : n_bins;
     for (int r = a0; r < a1; ++r) {
-        if (lo_s[r] < 0) lo_s[r] = chunk_lo[tid];
-        if (hi_s[r] >= n_bins) hi_s[r] = chunk_hi[tid];
+        if (lo_s[r] < 0) lo_s[r] = ex_lo;
+        if (hi_s[r] >= n_bins) hi_s[r] = ex_hi;
     }
     __syncthreads();
 
