@@ -90,6 +90,22 @@ def test_correct_jungfrau_frames_bit_exact(dev, jungfrau):
     assert np.array_equal(got[~bad].view(np.uint32), want[~bad].view(np.uint32))
 
 
+@pytest.mark.parametrize("n", [1, 2])
+def test_correct_few_frames_bit_exact(dev, jungfrau, n):
+    """One or two frames take the per-word calibration path."""
+    g, sc, geo, raw, ped, gain = jungfrau
+    _say("case: correct, jungfrau-4m, frames", n)
+    raw = raw[:n].copy()
+    raw[n - 1, 4321:4321 + 13] = (2 << 14) | 700  # invalid gain code
+    out, n_bad = api.correct(torch.from_numpy(raw).to(dev), torch.from_numpy(ped).to(dev),
+                             torch.from_numpy(gain).to(dev), geo.norm)
+    got = out.cpu().numpy()
+    want, bad = sc.frames_from_raw(raw)
+    assert n_bad.cpu().tolist()[-1] == 13
+    assert np.array_equal(np.isnan(got), bad)
+    assert np.array_equal(got[~bad].view(np.uint32), want[~bad].view(np.uint32))
+
+
 def test_correct_ragged_scalar_path(dev):
     _say("case: correct, ragged 1003 pixels")
     rng = np.random.default_rng(5)
