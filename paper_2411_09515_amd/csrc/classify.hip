@@ -12,8 +12,9 @@
 // (v - mu > n_pick sigma_eff), peak candidate (v - mu >= snr sigma_eff) and
 // peak (the patch test of the peak finder, evaluated from LDS).
 //
-// Ordered output without atomics: tiles of kTile consecutive pixels of one
-// frame count their kept pixels and peaks (k_tile_counts), one work-group
+// Ordered output without atomics: tiles of consecutive pixels of one frame
+// (256 threads x 32 pixels; x 8 for one or two frames) count their kept
+// pixels and peaks (k_tile_counts), one work-group
 // per frame turns the counts into exclusive offsets (k_tile_scan), and the
 // tiles write their entries in pixel order at those offsets (k_tile_write),
 // computing peak records on the way.
@@ -32,8 +33,12 @@ namespace ss {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kPPT = 32;  // consecutive pixels per thread
-constexpr int kTile = kBlock * kPPT;
+// consecutive pixels per thread of the compaction: 32 for batches, 8 for one
+// or two frames (four times the tiles, so that a single frame still fills
+// the device); the workspace holds counts for the smaller tiles
+constexpr int kPPT = 32;
+constexpr int kPPTFew = 8;
+constexpr int kFewFrames = 2;
 constexpr int kNW = kBlock / kWave;
 constexpr int kTableBlock = 256;
 
@@ -61,7 +66,9 @@ struct Workspace {
 
 constexpr uint8_t kValid = 1, kKeep = 2, kCand = 4, kPeak = 8;
 
-size_t tiles_of(int64_t n_pix) { return size_t((n_pix + kTile - 1) / kTile); }
+size_t tiles_of(int64_t n_pix, int ppt = kPPTFew) {
+    return size_t((n_pix + int64_t(kBlock) * ppt - 1) / (int64_t(kBlock) * ppt));
+}
 
 size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
 
@@ -567,17 +574,18 @@ __device__ inline uint32_t wave_inclusive_scan(uint32_t x) {
     return x;
 }
 
-// Kept / peak bits of the kPPT consecutive pixels of thread tid in a tile:
+// Kept / peak bits of the PPT consecutive pixels of thread tid in a tile:
 // 8-byte loads when every frame's bits start 8-byte aligned (n_pix % 8 ==
 // 0), byte loads otherwise.
-template <bool KEEP, bool PEAKS>
+template <bool KEEP, bool PEAKS, int PPT>
 __device__ inline void tile_masks(const uint8_t *__restrict__ bits, int64_t n_pix, int64_t p0, uint32_t &kmask,
                                   uint32_t &pmask) {
+    static_assert(PPT % 8 == 0 && PPT <= 32, "whole 8-byte words, one 32-bit mask");
     kmask = 0;
     pmask = 0;
-    if (p0 + kPPT <= n_pix && (n_pix % 8) == 0) {
+    if (p0 + PPT <= n_pix && (n_pix % 8) == 0) {
 #pragma unroll
-        for (int q = 0; q < kPPT / 8; ++q) {
+        for (int q = 0; q < PPT / 8; ++q) {
             const uint2 w = *reinterpret_cast<const uint2 *>(bits + p0 + 8 * q);
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
@@ -587,7 +595,7 @@ __device__ inline void tile_masks(const uint8_t *__restrict__ bits, int64_t n_pi
             }
         }
     } else {
-        for (int k = 0; k < kPPT; ++k) {
+        for (int k = 0; k < PPT; ++k) {
             const uint8_t b = p0 + k < n_pix ? bits[p0 + k] : 0;
             if (KEEP && (b & kKeep)) kmask |= 1u << k;
             if (PEAKS && (b & kPeak)) pmask |= 1u << k;
@@ -613,14 +621,14 @@ __device__ inline uint32_t block_exclusive_scan(uint32_t mine, uint32_t *wave_to
     return before;
 }
 
-// Per tile: packed count of kept pixels and peaks (each at most kTile).
-template <bool KEEP, bool PEAKS>
+// Per tile: packed count of kept pixels and peaks (each at most kBlock * PPT).
+template <bool KEEP, bool PEAKS, int PPT>
 __global__ __launch_bounds__(kBlock) void k_tile_counts(ClassArgs a) {
     __shared__ uint32_t wave_tot[kNW];
     const int tile = blockIdx.x, f = blockIdx.y;
-    const int64_t p0 = int64_t(tile) * kTile + int64_t(kPPT) * threadIdx.x;
+    const int64_t p0 = (int64_t(tile) * kBlock + threadIdx.x) * PPT;
     uint32_t kmask, pmask;
-    tile_masks<KEEP, PEAKS>(a.ws.bits + int64_t(f) * a.n_pix, a.n_pix, p0, kmask, pmask);
+    tile_masks<KEEP, PEAKS, PPT>(a.ws.bits + int64_t(f) * a.n_pix, a.n_pix, p0, kmask, pmask);
     const uint32_t mine = uint32_t(__popc(kmask)) | (uint32_t(__popc(pmask)) << 16);
     const uint32_t x = uint32_t(wave_sum(int(mine)));
     if ((threadIdx.x & (kWave - 1)) == 0) wave_tot[threadIdx.x / kWave] = x;
@@ -677,17 +685,17 @@ __global__ __launch_bounds__(kScanBlock) void k_tile_scan(ClassArgs a) {
 
 // Per tile: kept pixels and peak records in pixel order at the tile's
 // offsets; entries beyond the capacities are dropped.
-template <bool KEEP, bool PEAKS>
+template <bool KEEP, bool PEAKS, int PPT>
 __global__ __launch_bounds__(kBlock) void k_tile_write(ClassArgs a) {
     __shared__ uint32_t wave_tot[kNW];
     const int tile = blockIdx.x, f = blockIdx.y;
-    const int64_t p0 = int64_t(tile) * kTile + int64_t(kPPT) * threadIdx.x;
+    const int64_t p0 = (int64_t(tile) * kBlock + threadIdx.x) * PPT;
     const float *__restrict__ fr = a.frames + int64_t(f) * a.n_pix;
     const uint8_t *__restrict__ bits = a.ws.bits + int64_t(f) * a.n_pix;
     // the tile's offsets do not depend on the scan below: load them first
     const uint64_t toff = a.ws.offsets[int64_t(f) * a.tiles + tile];
     uint32_t kmask, pmask;
-    tile_masks<KEEP, PEAKS>(bits, a.n_pix, p0, kmask, pmask);
+    tile_masks<KEEP, PEAKS, PPT>(bits, a.n_pix, p0, kmask, pmask);
     const uint32_t mine = uint32_t(__popc(kmask)) | (uint32_t(__popc(pmask)) << 16);
     uint32_t total;
     const uint32_t before = block_exclusive_scan(mine, wave_tot, total);
@@ -741,12 +749,18 @@ __global__ __launch_bounds__(kBlock) void k_tile_write(ClassArgs a) {
     }
 }
 
-template <bool KEEP, bool PEAKS>
+template <bool KEEP, bool PEAKS, int PPT>
 void launch_compaction(const ClassArgs &a, hipStream_t stream) {
     const dim3 grid(uint32_t(a.tiles), uint32_t(a.n_frames));
-    k_tile_counts<KEEP, PEAKS><<<grid, kBlock, 0, stream>>>(a);
+    k_tile_counts<KEEP, PEAKS, PPT><<<grid, kBlock, 0, stream>>>(a);
     k_tile_scan<KEEP, PEAKS><<<dim3(uint32_t(a.n_frames)), kScanBlock, 0, stream>>>(a);
-    k_tile_write<KEEP, PEAKS><<<grid, kBlock, 0, stream>>>(a);
+    k_tile_write<KEEP, PEAKS, PPT><<<grid, kBlock, 0, stream>>>(a);
+}
+
+template <bool KEEP, bool PEAKS>
+void launch_compaction(const ClassArgs &a, bool few, hipStream_t stream) {
+    if (few) launch_compaction<KEEP, PEAKS, kPPTFew>(a, stream);
+    else launch_compaction<KEEP, PEAKS, kPPT>(a, stream);
 }
 
 
@@ -1012,7 +1026,8 @@ extern "C" int ss_classify(const float *frames, const uint8_t *mask, int32_t n_f
         return SS_EINVAL;
     if (ws_bytes < workspace_bytes(n_frames, n_pix, radial->n_bins)) return SS_ESIZE;
 
-    const int32_t tiles = int32_t(tiles_of(n_pix));
+    const bool few = n_frames <= kFewFrames;
+    const int32_t tiles = int32_t(tiles_of(n_pix, few ? kPPTFew : kPPT));
     Workspace ws = carve(workspace, n_frames, n_pix, radial->n_bins);
     k_profile_table<<<dim3(uint32_t(n_frames)), kTableBlock, 0, stream>>>(
         profile->mean, profile->std, profile->n_members, radial->n_bins, ws, tiles, keep ? n_kept : nullptr,
@@ -1079,9 +1094,9 @@ extern "C" int ss_classify(const float *frames, const uint8_t *mask, int32_t n_f
     a.peak_capacity = peak_capacity;
     a.n_peaks = n_peaks;
     a.ws = ws;
-    if (keep && pk) launch_compaction<true, true>(a, stream);
-    else if (keep) launch_compaction<true, false>(a, stream);
-    else launch_compaction<false, true>(a, stream);
+    if (keep && pk) launch_compaction<true, true>(a, few, stream);
+    else if (keep) launch_compaction<true, false>(a, few, stream);
+    else launch_compaction<false, true>(a, few, stream);
     SS_RETURN_IF_LAUNCH_FAILED();
     return SS_OK;
 }
