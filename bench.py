@@ -391,6 +391,9 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the mixed-detector batch")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
     ap.add_argument("--no-densify", action="store_true", help="skip the densification timing")
+    ap.add_argument("--workers", type=int, default=0,
+                    help="input-generation processes (default: up to 16); 1 generates in-process, "
+                         "no fork, as runs under a profiler need")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 1 GiB device copy (a known-size reference for HBM counters)")
     args = ap.parse_args()
@@ -400,7 +403,7 @@ def main():
         return 2
 
     t0 = time.perf_counter()
-    workers = min(16, os.cpu_count() or 1)
+    workers = args.workers if args.workers > 0 else min(16, os.cpu_count() or 1)
     raw_np = make_inputs(args.frames, workers)
     train_np = make_training(args.train_frames, workers)
     uneven_np, rings_np = make_extra(workers, not args.no_batched, not args.no_serve)
