@@ -31,7 +31,8 @@
  *   to `stream` through events (so the call still completes in `stream`
  *   order, and can be captured in a graph).  The side streams and their
  *   events are created once per device, on first use, and kept until the
- *   process ends; that is the library's only state.
+ *   process ends.  The other piece of library state is the device array that
+ *   serves ss_classify_noalloc as workspace (one per GPU).
  */
 #ifndef SIGSEP_H
 #define SIGSEP_H
@@ -323,6 +324,30 @@ int ss_classify(const float *frames, const uint8_t *mask, int32_t n_frames,
                 uint32_t *kept_index, float *kept_value, int64_t capacity, int64_t *n_kept,
                 ss_peak *peaks, int64_t peak_capacity, int64_t *n_peaks,
                 void *workspace, size_t workspace_bytes, hipStream_t stream);
+
+/*
+ * ss_classify_noalloc -- ss_classify for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): same arguments and results, without the workspace.  The
+ * workspace is a file-scope device array of SS_CLASSIFY_SCRATCH_BYTES bytes
+ * inside the library, one per GPU, held from the library's load until the
+ * process ends; its device address is looked up once per device on the
+ * first call made with that device current.  The call allocates and frees
+ * nothing.  Every call on one GPU uses that GPU's array, which keeps the last
+ * call's contents (each call writes every byte it reads first, so nothing
+ * needs clearing): calls that overlap on one GPU (different streams without
+ * ordering, or different host threads) race and give undefined results.
+ * Errors: those of ss_classify; SS_ESIZE also when
+ * ss_classify_workspace(n_frames, height * width, radial->n_bins) exceeds
+ * SS_CLASSIFY_SCRATCH_BYTES (checked before any device call), SS_EHIP when
+ * the array's address cannot be obtained.
+ */
+#define SS_CLASSIFY_SCRATCH_BYTES (64u << 20)
+int ss_classify_noalloc(const float *frames, const uint8_t *mask, int32_t n_frames,
+                        int32_t height, int32_t width, const ss_radial *radial,
+                        const ss_profile *profile, const ss_params *params,
+                        uint32_t *kept_index, float *kept_value, int64_t capacity, int64_t *n_kept,
+                        ss_peak *peaks, int64_t peak_capacity, int64_t *n_peaks, hipStream_t stream);
 
 /* ss_compress -- the sparsification half of ss_classify (Sec. 3). */
 int ss_compress(const float *frames, const uint8_t *mask, int32_t n_frames,

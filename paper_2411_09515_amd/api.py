@@ -390,6 +390,20 @@ def classify(frames, geom: Geometry, profile, params: Params, capacity=0, peak_c
     return out
 
 
+def classify_noalloc(frames, geom: Geometry, profile, params: Params, out, capacity, peak_capacity, mask=None):
+    """``classify`` through ss_classify_noalloc: the library's own device array
+    serves as workspace (nothing is allocated); ``out`` holds the caller's
+    output tensors (kept_index, kept_value, n_kept, peaks, n_peaks)."""
+    _need_device(frames, mask, *out.values())
+    F = frames.shape[0]
+    args = (_p(frames), _p(mask), F, geom.height, geom.width, ctypes.byref(geom.radial()),
+            ctypes.byref(profile_c(profile)), ctypes.byref(params.c()))
+    B.check("ss_classify_noalloc", B.lib().ss_classify_noalloc(
+        *args, _p(out.get("kept_index")), _p(out.get("kept_value")), capacity, _p(out.get("n_kept")),
+        _p(out.get("peaks")), peak_capacity, _p(out.get("n_peaks")), _stream()))
+    return out
+
+
 def compress(frames, geom, profile, params, capacity, mask=None, workspace=None):
     _need_device(frames, mask, workspace)
     F = frames.shape[0]

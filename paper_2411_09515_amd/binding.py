@@ -31,11 +31,12 @@ SS_MLP_OFF_B2, SS_MLP_OFF_W3, SS_MLP_OFF_B3 = 6208, 6272, 7296
 SS_MLP_PARAMS = 7312
 SS_VETO_BINS = 256
 SS_VETO_COUNTERS = 4 + 2 * SS_VETO_BINS
+SS_CLASSIFY_SCRATCH_BYTES = 64 << 20
 
 EXPORTED = (
     "ss_strerror", "ss_version", "ss_build_csr", "ss_csr_schedule", "ss_class_rows", "ss_radial_coords",
     "ss_correct",
-    "ss_integrate_csr", "ss_sigma_clip", "ss_classify_workspace", "ss_classify",
+    "ss_integrate_csr", "ss_sigma_clip", "ss_classify_workspace", "ss_classify", "ss_classify_noalloc",
     "ss_compress", "ss_peakfind",
     "ss_clip_features", "ss_surrogate_targets", "ss_mlp_forward", "ss_mlp_grad_workspace", "ss_mlp_grad",
     "ss_mlp_adam", "ss_sigma_clip_surrogate", "ss_sigma_clip_batches",
@@ -125,6 +126,9 @@ def lib():
         L.ss_classify.restype = ctypes.c_int
         L.ss_classify.argtypes = [vp, vp, i32, i32, i32, P(Radial), P(Profile), P(Params), vp, vp, i64, vp,
                                   vp, i64, vp, vp, sz, vp]
+        L.ss_classify_noalloc.restype = ctypes.c_int
+        L.ss_classify_noalloc.argtypes = [vp, vp, i32, i32, i32, P(Radial), P(Profile), P(Params), vp, vp, i64,
+                                          vp, vp, i64, vp, vp]
         L.ss_compress.restype = ctypes.c_int
         L.ss_compress.argtypes = [vp, vp, i32, i32, i32, P(Radial), P(Profile), P(Params), vp, vp, i64, vp,
                                   vp, sz, vp]

@@ -26,6 +26,7 @@
 // and accumulates the counters a live veto threshold is chosen from.
 
 #include <cmath>
+#include <mutex>
 
 #include "common.h"
 
@@ -1099,6 +1100,63 @@ extern "C" int ss_classify(const float *frames, const uint8_t *mask, int32_t n_f
     else launch_compaction<false, true>(a, few, stream);
     SS_RETURN_IF_LAUNCH_FAILED();
     return SS_OK;
+}
+
+// ---- classification without allocation ------------------------------------
+
+namespace {
+
+// The workspace of ss_classify_noalloc: one array per device, held from the
+// library's load until the process ends.  In host code `scratch` is only a
+// host-side stand-in for the symbol; the device address comes from
+// hipGetSymbolAddress (once per device, with that device current) and is the
+// only handle ever passed to kernels or copies.
+static __device__ __align__(256) uint8_t scratch[SS_CLASSIFY_SCRATCH_BYTES];
+
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch[kScratchDevices] = {};
+
+int scratch_of_current_device(void **out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kScratchDevices) {
+        (void)hipGetLastError();
+        return SS_EHIP;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch[dev] == nullptr) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || p == nullptr) {
+            (void)hipGetLastError();
+            return SS_EHIP;
+        }
+        g_scratch[dev] = p;
+    }
+    *out = g_scratch[dev];
+    return SS_OK;
+}
+
+}  // namespace
+
+extern "C" int ss_classify_noalloc(const float *frames, const uint8_t *mask, int32_t n_frames, int32_t height,
+                                   int32_t width, const ss_radial *radial, const ss_profile *profile,
+                                   const ss_params *p, uint32_t *kept_index, float *kept_value, int64_t capacity,
+                                   int64_t *n_kept, ss_peak *peaks, int64_t peak_capacity, int64_t *n_peaks,
+                                   hipStream_t stream) {
+    // sizes first, so that a call too large for the array touches no device state
+    if (!radial || !profile || !p) return SS_EINVAL;
+    if (n_frames < 0 || height < 0 || width < 0) return SS_ESIZE;
+    const int64_t n_pix = int64_t(height) * width;
+    if (n_pix >= (int64_t(1) << 29) || radial->n_bins <= 0 || radial->n_bins > SS_MAX_BINS) return SS_ESIZE;
+    if (ss::workspace_bytes(n_frames, n_pix, radial->n_bins) > size_t(SS_CLASSIFY_SCRATCH_BYTES)) return SS_ESIZE;
+    if (n_frames == 0)  // nothing is enqueued: the argument checks of ss_classify only
+        return ss_classify(frames, mask, n_frames, height, width, radial, profile, p, kept_index, kept_value,
+                           capacity, n_kept, peaks, peak_capacity, n_peaks, nullptr, 0, stream);
+    void *ws = nullptr;
+    const int rc = scratch_of_current_device(&ws);
+    if (rc != SS_OK) return rc;
+    return ss_classify(frames, mask, n_frames, height, width, radial, profile, p, kept_index, kept_value, capacity,
+                       n_kept, peaks, peak_capacity, n_peaks, ws, size_t(SS_CLASSIFY_SCRATCH_BYTES), stream);
 }
 
 extern "C" int ss_compress(const float *frames, const uint8_t *mask, int32_t n_frames, int32_t height,

@@ -207,3 +207,24 @@ def test_densify_veto_and_pack_reject_bad_arguments_before_launch():
     assert L.ss_pack_results(fake, fake, 8, fake, fake, 4, fake, 2, None, fake, fake, fake, None) == B.SS_EINVAL
     assert L.ss_pack_results(fake, fake, 8, fake, None, 4, fake, 2, fake, fake, fake, fake, None) == B.SS_EINVAL
     assert L.ss_pack_results(fake, None, 8, fake, None, 4, None, 2, fake, fake, fake, None, None) == B.SS_EINVAL
+
+
+def test_classify_noalloc_refuses_oversize_before_any_device_call():
+    """Sizes beyond the library's array are refused on the host; a call with
+    no frames enqueues nothing."""
+    L = B.lib()
+    g = synth.JUNGFRAU4M
+    ref = ctypes.byref
+    radial = B.Radial(g.n_bins, 0.025, 0.05, 4096)
+    prof = B.Profile(4096, 4096, 4096, 4096, 4096, 4096, 4096)
+    p = api.Params().c()
+    assert int(L.ss_classify_workspace(16, g.n_pix, g.n_bins)) > B.SS_CLASSIFY_SCRATCH_BYTES
+    args = (ctypes.c_void_p(4096), None, 16, g.height, g.width, ref(radial), ref(prof), ref(p),
+            ctypes.c_void_p(4096), ctypes.c_void_p(4096), 16, ctypes.c_void_p(4096), None, 0, None, None)
+    assert L.ss_classify_noalloc(*args) == B.SS_ESIZE
+    big = (ctypes.c_void_p(4096), None, 1, 1 << 15, 1 << 15) + args[5:]
+    assert L.ss_classify_noalloc(*big) == B.SS_ESIZE
+    none = (ctypes.c_void_p(4096), None, 0) + args[3:]
+    assert L.ss_classify_noalloc(*none) == B.SS_OK
+    assert L.ss_classify_noalloc(None, None, 1, 4, 4, None, ref(prof), ref(p), None, None, 0, None, None, 0,
+                                 None, None) == B.SS_EINVAL
