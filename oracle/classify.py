@@ -8,8 +8,12 @@ beyond the first and last non-empty bins (``numpy.interp``).  The same
 mu_i, sigma_i serve sparsification, densification and the peak finder.
 sigma_eff = sqrt(sigma^2 + noise^2), with the noise level of Sec. 4.1.
 
-Frames hold the corrected intensity v = signal / norm of eq. norm, the units
-of the stored profile; kept values and peak intensities are in those units.
+Every decision is taken on the corrected intensity v = signal / norm of
+eq. norm, the units of the stored profile, formed in float64: a frame is
+either the float32 signal with its ``norm`` (then v = signal / norm), or,
+with ``norm=None``, already in those units (norm = 1).  Kept values and peak
+intensities are in units of v; the stored sparse format holds a kept value
+as float32 (the rounding of v).
 
 Sparsification (Sec. 3): keep pixel i when it is valid (not masked, finite)
 and v_i - mu_i > n_pick * sigma_eff_i (strict, one-sided: low outliers are
@@ -50,20 +54,22 @@ def background_at(position, centres, profile):
     return mu, sd
 
 
-def pixel_state(frame, mask, position, centres, profile, noise=0.0):
+def pixel_state(frame, mask, position, centres, profile, noise=0.0, norm=None):
     """v, mu, sigma_eff and validity for every pixel of one frame (flat arrays)."""
     s = np.asarray(frame, dtype=np.float64).reshape(-1)
     valid = np.isfinite(s)
     if mask is not None:
         valid &= np.asarray(mask).reshape(-1) == 0
+    if norm is not None:
+        s = s / np.asarray(norm, dtype=np.float64).reshape(-1)
     v = np.where(valid, s, 0.0)
     mu, sd = background_at(position, centres, profile)
     return v, mu, np.sqrt(sd * sd + noise * noise), valid
 
 
-def compress(frame, mask, position, centres, profile, n_pick=3.0, noise=0.0):
+def compress(frame, mask, position, centres, profile, n_pick=3.0, noise=0.0, norm=None):
     """Sparse frame: (indices int64 ascending, values float64 = v)."""
-    v, mu, se, valid = pixel_state(frame, mask, position, centres, profile, noise)
+    v, mu, se, valid = pixel_state(frame, mask, position, centres, profile, noise, norm)
     keep = valid & (v - mu > n_pick * se)
     idx = np.nonzero(keep)[0]
     return idx, v[idx]
@@ -138,9 +144,9 @@ def _shift(a, dy, dx, fill):
 
 
 def peakfind(frame, mask, height, width, position, centres, profile,
-             snr=3.0, patch=3, min_count=3, noise=0.0):
+             snr=3.0, patch=3, min_count=3, noise=0.0, norm=None):
     """Peaks of one frame as a structured array (PEAK_DTYPE), ascending index."""
-    v, mu, se, valid = pixel_state(frame, mask, position, centres, profile, noise)
+    v, mu, se, valid = pixel_state(frame, mask, position, centres, profile, noise, norm)
     H, W = height, width
     cand = valid & (v - mu >= snr * se)
     V = v.reshape(H, W)
@@ -185,9 +191,9 @@ def peakfind(frame, mask, height, width, position, centres, profile,
 
 
 def peakfind_loops(frame, mask, height, width, position, centres, profile,
-                   snr=3.0, patch=3, min_count=3, noise=0.0):
+                   snr=3.0, patch=3, min_count=3, noise=0.0, norm=None):
     """The same peak rule with explicit Python loops (small frames only)."""
-    v, mu, se, valid = pixel_state(frame, mask, position, centres, profile, noise)
+    v, mu, se, valid = pixel_state(frame, mask, position, centres, profile, noise, norm)
     H, W = height, width
     cand = valid & (v - mu >= snr * se)
     h = patch // 2

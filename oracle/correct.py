@@ -13,9 +13,11 @@ reference, so this is a reading, **parity unpinned** against the paper:
 * the corrected frame is stored as float32, the precision the paper gives
   for pre-processed data; the arithmetic before that rounding is float64.
 
-``normalise`` then applies the normalisation of eq. norm, I = signal / norm,
-again in float64 and stored as a float32 frame: this corrected-intensity
-frame is what the later stages consume.
+``normalise`` applies the normalisation of eq. norm, I = signal / norm, in
+float64 and stores it as a float32 frame (the corrected frame a correction
+stage hands out).  The statistics and the classification do not take that
+rounded frame: they take the float32 signal and norm and form I = signal /
+norm in float64 themselves (``oracle.stats``, ``oracle.classify``).
 """
 
 from __future__ import annotations

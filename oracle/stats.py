@@ -2,13 +2,14 @@
 
 Sec. 2.2 defines, for the members of one radial bin (pixel i with CSR
 coefficient c and normalisation norm_i).  The frames handed to these
-functions hold the corrected intensity v = signal / norm of eq. norm; norm
-itself enters through the weights and the Poisson variance only.
+functions hold the pre-processed ``signal`` of eq. norm (the numerator: raw
+minus dark, a 32-bit value per pixel, Sec. 1.2); every quantity below is
+formed from it and from ``norm`` in float64:
 
   weight       omega_i = c * norm_i                          (eq. omega)
   value        v_i = signal_i / norm_i                       (eq. norm)
-  Omega        = sum omega_i,   OmegaOmega = sum omega_i^2  (eqs. omega, omegaomega)
-  V            = sum omega_i v_i = sum c signal_i            (eq. Vp)
+  Omega        = sum c norm_i,  OmegaOmega = sum omega_i^2  (eqs. omega, omegaomega)
+  V            = sum c signal_i                              (eqs. avg, Vp)
   mean <I>     = V / Omega                                   (eqs. avg, weighted_avg)
   VV           = sum omega_i^2 (v_i - <I>)^2                 (eq. VVp, second pass)
   std^2        = VV / OmegaOmega                             (eqs. varA, std2)
@@ -44,6 +45,7 @@ logarithm and size = |E_k|; when size <= sqrt(2 pi) nothing is removed.
 from __future__ import annotations
 
 import math
+from typing import NamedTuple
 
 import numpy as np
 
@@ -58,11 +60,13 @@ def chauvenet(size) -> float:
     return math.sqrt(2.0 * math.log(size / SQRT_2PI))
 
 
-def moments(v, omega, pvar=None):
+def moments(v, omega, pvar=None, csig=None):
     """Weighted statistics of one member set (two-pass).
 
     v: values signal/norm; omega: weights c*norm; pvar: optional c^2 sigma^2
-    per member (Poisson numerator terms).  Returns a dict of float64.
+    per member (Poisson numerator terms); csig: optional c*signal per member,
+    whose sum is V of eq. avg (without it V = sum omega v, the same sum).
+    Returns a dict of float64.
     """
     v = np.asarray(v, dtype=np.float64)
     omega = np.asarray(omega, dtype=np.float64)
@@ -72,7 +76,7 @@ def moments(v, omega, pvar=None):
         return out
     Omega = float(np.sum(omega))
     OO = float(np.sum(omega * omega))
-    V = float(np.sum(omega * v))
+    V = float(np.sum(omega * v)) if csig is None else float(np.sum(np.asarray(csig, dtype=np.float64)))
     mean = V / Omega
     VV = float(np.sum(omega * omega * (v - mean) ** 2))
     out.update(Omega=Omega, OmegaOmega=OO, V=V, VV=VV, mean=mean,
@@ -83,29 +87,40 @@ def moments(v, omega, pvar=None):
     return out
 
 
-def bin_members(frame, norm, csr, r, mask=None, dark_var=0.0):
-    """Members of bin r for one frame: (pixel, c, v, omega, c^2 sigma^2).
+class Members(NamedTuple):
+    """The members of one bin in one frame, aligned arrays (float64)."""
 
-    frame holds v = signal / norm.  A pixel is a member when it is not
-    masked and its value is finite.  sigma^2 is the variance of the pixel's
-    signal, max(v * norm, 0) + sigma_dark^2.
+    pix: np.ndarray    # pixel index
+    c: np.ndarray      # CSR coefficient c[i, r]
+    v: np.ndarray      # signal / norm
+    omega: np.ndarray  # c * norm
+    pvar: np.ndarray   # c^2 sigma^2, sigma^2 = max(signal, 0) + sigma_dark^2
+    csig: np.ndarray   # c * signal
+
+
+def bin_members(signal, norm, csr, r, mask=None, dark_var=0.0) -> Members:
+    """Members of bin r for one frame.
+
+    signal: the pre-processed frame (numerator of eq. norm); norm: the
+    normalisation per pixel, or None for 1.  A pixel is a member when it is
+    not masked and its signal is finite.
     """
     pix, c = csr.row(r)
-    v = frame[pix].astype(np.float64)
+    s = signal[pix].astype(np.float64)
     nr = np.ones(pix.size) if norm is None else norm[pix].astype(np.float64)
-    ok = np.isfinite(v)
+    ok = np.isfinite(s)
     if mask is not None:
         ok &= mask[pix] == 0
-    pix, c, v, nr = pix[ok], c[ok], v[ok], nr[ok]
-    var = np.maximum(v * nr, 0.0) + dark_var
-    return pix, c, v, c * nr, c * c * var
+    pix, c, s, nr = pix[ok], c[ok], s[ok], nr[ok]
+    var = np.maximum(s, 0.0) + dark_var
+    return Members(pix, c, s / nr, c * nr, c * c * var, c * s)
 
 
-def _clip_bin(v, omega, pvar, cutoff, max_iter, model):
+def _clip_bin(v, omega, pvar, cutoff, max_iter, model, csig=None):
     keep = np.ones(v.size, dtype=bool)
     n_iter, converged, margin = 0, 0, np.inf
     for _ in range(max_iter):
-        m = moments(v[keep], omega[keep], pvar[keep])
+        m = moments(v[keep], omega[keep], pvar[keep], None if csig is None else csig[keep])
         n = cutoff if cutoff > 0 else chauvenet(int(keep.sum()))
         spread = m["std_p"] if model == POISSON else m["std"]
         thr = n * spread
@@ -121,12 +136,12 @@ def _clip_bin(v, omega, pvar, cutoff, max_iter, model):
     return keep, n_iter, converged, margin
 
 
-def sigma_clip(frame, norm, csr, mask=None, cutoff=3.0, max_iter=5,
+def sigma_clip(signal, norm, csr, mask=None, cutoff=3.0, max_iter=5,
                error_model=AZIMUTHAL, dark_var=0.0, return_keep=False, return_margin=False):
     """Sigma-clipped profile of one frame (max_iter = 0 gives the plain average).
 
-    frame: corrected intensity v = signal / norm, float [N] (NaN = invalid);
-    norm: float [N] or None (= 1), for the weights and the Poisson variance.
+    signal: the pre-processed frame, float [N] (NaN = invalid); norm: float
+    [N] or None (= 1): v = signal / norm, weights c * norm, Poisson variance.
     With ``return_margin`` also ``margin``: per bin, the smallest relative
     distance | |v - mean_k| - n_k std_k | / (n_k std_k) of any member to the
     threshold over the passes run (inf when no pass compared anything); it
@@ -136,7 +151,7 @@ def sigma_clip(frame, norm, csr, mask=None, cutoff=3.0, max_iter=5,
     every bin (list of bool arrays aligned with the members of that bin).
     """
     nb = csr.n_bins
-    frame = np.asarray(frame).reshape(-1)
+    signal = np.asarray(signal).reshape(-1)
     norm = None if norm is None else np.asarray(norm).reshape(-1)
     mask = None if mask is None else np.asarray(mask).reshape(-1)
     out = dict(mean=np.zeros(nb), std=np.zeros(nb), sem=np.zeros(nb), sum_w=np.zeros(nb),
@@ -145,9 +160,9 @@ def sigma_clip(frame, norm, csr, mask=None, cutoff=3.0, max_iter=5,
     keeps = []
     margins = np.full(nb, np.inf)
     for r in range(nb):
-        pix, c, v, omega, pvar = bin_members(frame, norm, csr, r, mask, dark_var)
-        keep, n_iter, conv, margins[r] = _clip_bin(v, omega, pvar, cutoff, max_iter, error_model)
-        m = moments(v[keep], omega[keep], pvar[keep])
+        mb = bin_members(signal, norm, csr, r, mask, dark_var)
+        keep, n_iter, conv, margins[r] = _clip_bin(mb.v, mb.omega, mb.pvar, cutoff, max_iter, error_model, mb.csig)
+        m = moments(mb.v[keep], mb.omega[keep], mb.pvar[keep], mb.csig[keep])
         poisson_report = error_model in (POISSON, HYBRID)
         out["mean"][r] = m["mean"]
         out["std"][r] = m["std_p"] if poisson_report else m["std"]
@@ -157,7 +172,7 @@ def sigma_clip(frame, norm, csr, mask=None, cutoff=3.0, max_iter=5,
         out["n_iter"][r] = n_iter
         out["converged"][r] = conv
         if return_keep:
-            keeps.append((pix, keep))
+            keeps.append((mb.pix, keep))
     if return_keep:
         out["keep"] = keeps
     if return_margin:
@@ -165,7 +180,7 @@ def sigma_clip(frame, norm, csr, mask=None, cutoff=3.0, max_iter=5,
     return out
 
 
-def integrate(frame, norm, csr, mask=None, error_model=AZIMUTHAL, dark_var=0.0):
+def integrate(signal, norm, csr, mask=None, error_model=AZIMUTHAL, dark_var=0.0):
     """Azimuthal average with uncertainties, no clipping (eqs. avg .. sem2)."""
-    return sigma_clip(frame, norm, csr, mask, cutoff=3.0, max_iter=0,
+    return sigma_clip(signal, norm, csr, mask, cutoff=3.0, max_iter=0,
                       error_model=error_model, dark_var=dark_var)

@@ -127,8 +127,8 @@ def features(frame, norm, csr, mask=None):
     X = np.zeros((csr.n_bins, N_IN))
     st = np.zeros((csr.n_bins, 3))
     for r in range(csr.n_bins):
-        _, _, v, omega, _ = S.bin_members(frame, norm, csr, r, mask)
-        X[r], st[r] = bin_features(v, omega)
+        mb = S.bin_members(frame, norm, csr, r, mask)
+        X[r], st[r] = bin_features(mb.v, mb.omega)
     return X, st
 
 
@@ -257,7 +257,8 @@ def surrogate_clip(frame, norm, csr, p, mask=None, cutoff=3.0, max_iter=32, wide
         n0, m0, s0 = st[r]
         if n0 < 2 or not (s0 > 0) or max_iter < 1:
             continue
-        _, _, v, omega, _ = S.bin_members(frame, normf, csr, r, maskf)
+        mb = S.bin_members(frame, normf, csr, r, maskf)
+        v, omega = mb.v, mb.omega
         mean_hat = m0 + y[r, 0] * s0
         std_hat = s0 * math.exp(y[r, 1])
         if n0 < MIN_MEMBERS or not (mean_hat - cutoff * (1.0 + widen) * std_hat > 0):

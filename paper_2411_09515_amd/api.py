@@ -522,6 +522,50 @@ def peaks_to_numpy(peaks_u8, n):
     return raw.reshape(-1).view(PEAK_DTYPE).copy() if raw.size else np.zeros(0, dtype=PEAK_DTYPE)
 
 
+# -- graph lifetimes -------------------------------------------------------------------------
+
+# A captured graph must not be destroyed while another capture is open on the
+# device: the destruction is an operation the capture forbids, and the
+# runtime aborts.  Captures therefore run inside ``capturing()``, which
+# pauses cyclic garbage collection (a collected object could own a graph)
+# and defers every graph released through ``release_graphs`` until no
+# capture is open.  Objects that capture (Pipeline, serve.Server) own their
+# graphs until ``close()``.
+_open_captures = 0
+_deferred_graphs = []
+
+
+class capturing:
+    """Context of one graph capture (re-entrant)."""
+
+    def __enter__(self):
+        global _open_captures
+        if _open_captures == 0:
+            gc.collect()
+            self._gc = gc.isenabled()
+            gc.disable()
+        _open_captures += 1
+        return self
+
+    def __exit__(self, *exc):
+        global _open_captures
+        _open_captures -= 1
+        if _open_captures == 0:
+            if getattr(self, "_gc", False):
+                gc.enable()
+            _deferred_graphs.clear()   # no capture open: the deferred graphs may go now
+        return False
+
+
+def release_graphs(graphs):
+    """Drop references to captured graphs (a list or dict of them, emptied);
+    while a capture is open they are kept until it closes."""
+    items = list(graphs.values()) if isinstance(graphs, dict) else list(graphs)
+    graphs.clear()
+    if _open_captures:
+        _deferred_graphs.extend(items)
+
+
 # -- the whole path ------------------------------------------------------------------------
 
 class Pipeline:
@@ -569,26 +613,33 @@ class Pipeline:
     def capture(self, raw):
         """Capture one pass over the raw frames in ``raw`` (a fixed device
         buffer the caller refills) as a HIP graph; ``replay`` then runs the
-        whole path with one launch.  The graph holds no memory sets."""
-        gc.collect()
-        was_enabled = gc.isenabled()
-        gc.disable()
-        try:
+        whole path with one launch.  The graph holds no memory sets and is
+        owned by the pipeline until ``close()`` (or the next capture)."""
+        with capturing():
+            self.close()
             side = torch.cuda.Stream(device=raw.device)
             side.wait_stream(torch.cuda.current_stream())
             with torch.cuda.stream(side):
                 self.run(raw)                   # eager first: nothing initialised inside the capture
             torch.cuda.current_stream().wait_stream(side)
             torch.cuda.synchronize(raw.device)
-            self.graph = torch.cuda.CUDAGraph()
-            with torch.cuda.graph(self.graph, stream=side):
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=side):
                 self.run(raw)
-        finally:
-            if was_enabled:
-                gc.enable()
-        return self.graph
+            self._graphs = [g]
+        return g
+
+    @property
+    def graph(self):
+        return self._graphs[0] if getattr(self, "_graphs", None) else None
 
     def replay(self):
         """The captured pass, on the current stream; returns the output tensors."""
         self.graph.replay()
         return self.out
+
+    def close(self):
+        """Release the captured graph (deferred while a capture is open)."""
+        if getattr(self, "_graphs", None):
+            torch.cuda.synchronize()
+            release_graphs(self._graphs)

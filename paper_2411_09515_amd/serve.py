@@ -27,7 +27,6 @@ from __future__ import annotations
 
 import collections
 import ctypes
-import gc
 import time
 from dataclasses import dataclass, field
 
@@ -56,6 +55,12 @@ class Request:
     peaks: np.ndarray = field(default=None, repr=False)
     mean: np.ndarray = field(default=None, repr=False)
     std: np.ndarray = field(default=None, repr=False)
+    # the rest of the profile, returned only by a Server with full_profile=True
+    sem: np.ndarray = field(default=None, repr=False)
+    sum_w: np.ndarray = field(default=None, repr=False)
+    n_members: np.ndarray = field(default=None, repr=False)
+    n_iter: np.ndarray = field(default=None, repr=False)
+    converged: np.ndarray = field(default=None, repr=False)
 
 
 class Detector:
@@ -81,9 +86,10 @@ class Detector:
 
 
 class _Slot:
-    def __init__(self, det: Detector, device, stream):
+    def __init__(self, det: Detector, device, stream, full_profile=False):
         F, N, nb = det.max_batch, det.geom.n_pix, det.geom.n_bins
         self.det = det
+        self.full_profile = full_profile
         self.raw = torch.empty((F, N), dtype=torch.int16, device=device)
         self.frames = torch.empty((F, N), dtype=torch.float32, device=device)
         self.n_invalid = torch.empty(F, dtype=torch.int64, device=device)
@@ -110,10 +116,14 @@ class _Slot:
         self.h_index = torch.empty(F * det.kept_capacity, dtype=torch.int32, pin_memory=True)
         self.h_value = torch.empty(F * det.kept_capacity, dtype=torch.float32, pin_memory=True)
         self.h_peaks = torch.empty((F * det.peak_capacity, B.PEAK_BYTES), dtype=torch.uint8, pin_memory=True)
+        self.h_rest = {}
+        if full_profile:
+            self.h_rest = {k: torch.empty((F, nb), dtype=self.profile[k].dtype, pin_memory=True)
+                           for k in ("sem", "sum_w", "n_members", "n_iter", "converged")}
         # touch every page of the pinned buffers now: first touches fault, and
         # would otherwise land inside the serving loop
         for t in (self.h_idx, self.h_counts, self.h_offsets, self.h_mean, self.h_std, self.h_index, self.h_value,
-                  self.h_peaks):
+                  self.h_peaks, *self.h_rest.values()):
             t.zero_()
         self.stream = stream
         self.graphs = {}     # batch size -> captured device work of one batch
@@ -163,7 +173,8 @@ class Server:
     so that per-request result arrays come from the heap (see
     ``_keep_result_buffers_on_the_heap``)."""
 
-    def __init__(self, detectors, hbm_budget=8 << 30, device="cuda", max_slots_per_detector=2, tune_malloc=True):
+    def __init__(self, detectors, hbm_budget=8 << 30, device="cuda", max_slots_per_detector=2, tune_malloc=True,
+                 full_profile=False):
         if tune_malloc:
             _keep_result_buffers_on_the_heap()
         self.detectors = list(detectors)
@@ -187,7 +198,7 @@ class Server:
             for i, d in enumerate(self.detectors):
                 b = d.slot_bytes()
                 if per_det[i] < max_slots_per_detector and used + b <= hbm_budget:
-                    self.slots.append(_Slot(d, self.device, self.streams[i]))
+                    self.slots.append(_Slot(d, self.device, self.streams[i], full_profile))
                     per_det[i] += 1
                     used += b
                     progress = True
@@ -214,6 +225,8 @@ class Server:
             slot.h_counts[1, :F].copy_(slot.out["n_peaks"][:F], non_blocking=True)
             slot.h_mean[:F].copy_(slot.profile["mean"][:F], non_blocking=True)
             slot.h_std[:F].copy_(slot.profile["std"][:F], non_blocking=True)
+            for k, h in slot.h_rest.items():
+                h[:F].copy_(slot.profile[k][:F], non_blocking=True)
             slot.ev_counts.record(slot.stream)
         slot.batch = batch
         slot.phase = 1
@@ -245,6 +258,8 @@ class Server:
             r.peaks = api.peaks_to_numpy(slot.h_peaks[p0:p1], p1 - p0)
             r.mean = slot.h_mean[f].numpy().copy()
             r.std = slot.h_std[f].numpy().copy()
+            for k, h in slot.h_rest.items():
+                setattr(r, k, h[f].numpy().copy())
             r.batch_size = F
             r.t_done = now
         slot.batch = []
@@ -255,13 +270,11 @@ class Server:
         graph (one launch per batch instead of one per kernel).  The graphs
         hold no copies to the host and no memory sets."""
         torch.cuda.synchronize(self.device)
-        # no garbage collection while capturing: collecting an unreachable
-        # graph of another object would destroy it in the middle of a capture
-        gc.collect()
-        was_enabled = gc.isenabled()
-        gc.disable()
-        try:
+        # the server owns its graphs until close(); no graph is destroyed while
+        # a capture is open (api.capturing defers releases, pauses collection)
+        with api.capturing():
             for s in self.slots:
+                api.release_graphs(s.graphs)
                 for F in range(1, s.det.max_batch + 1):
                     s.d_idx[:F].zero_()
                     with torch.cuda.stream(s.stream):
@@ -271,16 +284,14 @@ class Server:
                     with torch.cuda.graph(g, stream=s.stream):
                         s.device_work(F)
                     s.graphs[F] = g
-        finally:
-            if was_enabled:
-                gc.enable()
         torch.cuda.synchronize(self.device)
 
     def close(self):
-        """Release the captured graphs (before the device buffers they use)."""
+        """Release the captured graphs (before the device buffers they use;
+        deferred while a capture is open)."""
         torch.cuda.synchronize(self.device)
         for s in self.slots:
-            s.graphs.clear()
+            api.release_graphs(s.graphs)
 
     def warmup(self, graphs=True):
         """Graphs for every slot and batch size (unless ``graphs`` is False),

@@ -1,7 +1,9 @@
 """Continuous-batching service of four detectors (Jungfrau 1M, 4M, 9M, 16M):
 every frame's results in the mix (batched with other frames of its
 detector, batches of all detectors in flight together) are the same as when
-the frame is served alone.
+the frame is served alone, and one served frame per detector matches the
+FP64 oracle (profile through the replay, kept pixels and peaks; a tile and
+sampled bins for the two largest detectors).
 
 Tolerance: kept pixels, their values and the peaks identical; the profile
 within the clip's parity tolerance (a batch and a single frame run
@@ -56,10 +58,15 @@ def _same(a, b, label):
     tol = REL * np.abs(b.mean) + ABS_OF_MEAN * np.abs(b.mean)
     assert np.all(np.abs(a.mean - b.mean) <= tol), label
     assert np.all(np.abs(a.std - b.std) <= REL * np.abs(b.std) + ABS_OF_MEAN * np.abs(b.mean)), label
+    for k in ("n_members", "n_iter", "converged"):
+        assert np.array_equal(getattr(a, k), getattr(b, k)), (label, k)
 
 
-def test_results_are_the_same_alone_and_in_the_mix(dev, detectors):
-    server = serve.Server(detectors, hbm_budget=12 << 30, device=dev)
+@pytest.fixture(scope="module")
+def served(dev, detectors):
+    """Every ring frame served alone, then mixed Poisson arrivals served with
+    eager launches and with graph replays."""
+    server = serve.Server(detectors, hbm_budget=12 << 30, device=dev, full_profile=True)
     _say("case: alone, one request at a time")
     alone = {}
     for d in range(len(detectors)):
@@ -67,6 +74,7 @@ def test_results_are_the_same_alone_and_in_the_mix(dev, detectors):
             (r,), _ = server.run([serve.Request(det=d, ring_index=k, t_arrival=0.0)], realtime=False)
             assert r.batch_size == 1
             alone[(d, k)] = r
+    mixed = {}
     for mode in ("eager launches", "graph replays"):
         if mode == "graph replays":
             _say("case: capture every slot's batch sizes as graphs")
@@ -81,11 +89,57 @@ def test_results_are_the_same_alone_and_in_the_mix(dev, detectors):
         reqs = serve.poisson_arrivals([900, 600, 300, 200], 0.25, [RING] * len(detectors), seed=5)
         done, stats = server.run(reqs, realtime=True)
         _say(stats)
-        assert stats["frames"] == len(reqs) and all(np.isfinite(r.t_done) for r in done)
+        mixed[mode] = (done, stats, len(reqs))
+    server.close()
+    return alone, mixed
+
+
+def test_results_are_the_same_alone_and_in_the_mix(dev, served):
+    alone, mixed = served
+    for mode, (done, stats, n) in mixed.items():
+        assert stats["frames"] == n and all(np.isfinite(r.t_done) for r in done)
         assert stats["max_batches_in_flight"] >= 2          # batches overlap on the device
         assert max(r.batch_size for r in done) >= 2         # frames that waited were batched
         for r in done:
             _same(r, alone[(r.det, r.ring_index)], (mode, r.rid, r.det, r.ring_index, r.batch_size))
+
+
+# one served frame per detector against the oracle: the whole frame for 1M
+# and 4M; for 9M and 16M a 256 x 256 tile across the water ring (every bin
+# its pixels interpolate between) plus the six longest rows
+TILES = {"9m": True, "16m": True}
+
+
+@pytest.mark.parametrize("d", range(len(DETS)))
+def test_served_frame_matches_oracle(dev, served, d):
+    from parity import OracleScene
+    alone, mixed = served
+    name, g = DETS[d]
+    done, _, _ = mixed["graph replays"]
+    r = next(x for x in done if x.det == d)
+    _say(f"case: served {name} frame (ring {r.ring_index}, batch of {r.batch_size}) vs oracle")
+    sc = OracleScene(g)
+    raw = synth.uneven_frame(g, 100 + r.ring_index)[0].reshape(1, -1)
+    signal, _ = sc.signal_from_raw(raw)
+    gpu = {k: getattr(r, k) for k in ("mean", "std", "sem", "sum_w", "n_members", "n_iter", "converged")}
+    p = api.Params(cutoff=3.0, max_iter=5)
+    region = bins = None
+    if TILES.get(name):
+        cy, cx = int(g.centre_row), int(g.centre_col)
+        region = (cy + 200, cy + 456, cx + 250, cx + 506)
+        lens = np.diff(sc.csr.indptr)
+        bins = np.concatenate([sc.tile_bins(region), np.argsort(lens)[-6:]])
+    res, counts = sc.check_profile(gpu, signal[0], p, f"served {name}", bins=bins)
+    if bins is not None:
+        assert np.all(res["n_members"][sc.tile_bins(region)] > 0)   # the tile interpolates inside the sample
+    c = sc.check_classify(signal[0], gpu, res, r.kept_index, r.kept_value, r.peaks, p, f"served {name}",
+                          region=region)
+    _say(f"  {name}: bins {counts['bins']} (replayed {counts['replayed']}), kept {c['kept']} "
+         f"(excused {c['excused_keep']} px), peaks {c['peaks']} (excused {c['excused_cand']} px) "
+         f"of {c['valid']} valid px")
+    assert counts["unresolved"] == 0 and counts["replayed"] <= 1e-3 * counts["bins"] + 1
+    assert c["excused_keep"] <= 1e-3 * c["valid"] and c["excused_cand"] <= 1e-3 * c["valid"]
+    assert c["kept"] > 0
 
 
 def test_packed_results_match_the_per_frame_layout(dev):

@@ -138,7 +138,7 @@ def test_features_match_oracle(dev, small):
             if n == 0:
                 assert np.all(feats[f, r] == 0)
                 continue
-            _, _, v, _, _ = OS.bin_members(frames[f], None, sc.csr, r, sc.mask)
+            v = OS.bin_members(frames[f], None, sc.csr, r, sc.mask).v
             near = np.array([np.count_nonzero(np.abs(v - (st[r, 1] + t * st[r, 2])) <= MARGIN * st[r, 2])
                              for t in Q.THRESHOLDS])
             diff = np.abs(np.rint(feats[f, r, 3:] * n) - np.rint(X[r, 3:] * n))
@@ -181,7 +181,7 @@ def test_trained_surrogate_matches_oracle_and_saves_passes(dev, small):
                 # only where a decision of the oracle sits on a threshold within rounding
                 mh, sh = st[r, 1] + y[r, 0] * st[r, 2], st[r, 2] * np.exp(y[r, 1])
                 half = 3.0 * 1.1 * sh
-                _, _, v, omega, _ = OS.bin_members(test[f], None, sc.csr, r, sc.mask)
+                v = OS.bin_members(test[f], None, sc.csr, r, sc.mask).v
                 near = np.min(np.abs(np.abs(v - mh) - half)) / half
                 m = ref if ref["state"][r] == 1 else pl
                 for side in (m["mean"][r] - 3 * m["std"][r] - (mh - half), mh + half - m["mean"][r] - 3 * m["std"][r]):

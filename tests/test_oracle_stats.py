@@ -154,9 +154,35 @@ def test_weighted_mean_is_ratio_of_sums(rng):
     signal = rng.uniform(10, 100, n)
     norm = rng.uniform(0.3, 1.0, n)
     c = rng.uniform(0.05, 1.0, n)
-    out = S.integrate(signal / norm, norm, _OneRowCsr(c))
-    assert out["mean"][0] == pytest.approx(np.dot(c, signal) / np.dot(c, norm), rel=1e-13)
-    assert out["sum_w"][0] == pytest.approx(np.dot(c, norm), rel=1e-13)
+    out = S.integrate(signal, norm, _OneRowCsr(c))
+    assert out["mean"][0] == pytest.approx(np.dot(c, signal) / np.dot(c, norm), rel=1e-14)
+    assert out["sum_w"][0] == pytest.approx(np.dot(c, norm), rel=1e-14)
+
+
+def test_statistics_use_the_unrounded_quotient():
+    """The float32 signal and norm enter eq. avg and the deviations in
+    float64: the result is the exact-arithmetic value of the definition, not
+    the one of a float32-rounded corrected frame (which is off by up to 2^-24
+    per value).  Exact rational arithmetic decides."""
+    rng = np.random.default_rng(77)
+    n = 64
+    signal = rng.uniform(10, 100, n).astype(np.float32)
+    norm = (1.0 / rng.integers(3, 11, n)).astype(np.float32)   # quotients far from float32 values
+    c = rng.uniform(0.05, 1.0, n)
+    out = S.integrate(signal, norm, _OneRowCsr(c))
+    fc = [Fraction(float(x)) for x in c]
+    fs = [Fraction(float(x)) for x in signal]
+    fn = [Fraction(float(x)) for x in norm]
+    mean = sum(a * b for a, b in zip(fc, fs)) / sum(a * b for a, b in zip(fc, fn))
+    vv = sum((a * b) ** 2 * (s / b - mean) ** 2 for a, b, s in zip(fc, fn, fs))
+    oo = sum((a * b) ** 2 for a, b in zip(fc, fn))
+    assert abs(Fraction(out["mean"][0]) - mean) <= Fraction(1, 10 ** 14) * mean
+    assert out["std"][0] == pytest.approx(math.sqrt(vv / oo), rel=1e-13)
+    # the float32 corrected frame gives a measurably different mean
+    v32 = (signal.astype(np.float64) / norm).astype(np.float32).astype(np.float64)
+    w = c * norm.astype(np.float64)
+    m32 = np.dot(w, v32) / np.sum(w)
+    assert abs(m32 - float(mean)) > 1e3 * abs(out["mean"][0] - float(mean))
 
 
 def test_flat_image_any_split():
@@ -166,7 +192,7 @@ def test_flat_image_any_split():
         csr = G.build_csr(H, W, 75e-6, 0.003, 19.2, 20.7, 30, split)
         norm = np.linspace(0.5, 1.0, H * W)
         k = 37.25
-        out = S.integrate((k * norm) / norm, norm, csr)
+        out = S.integrate(k * norm, norm, csr)
         ne = out["n_members"] > 0
         assert ne.all()
         assert np.allclose(out["mean"][ne], k, rtol=1e-14)
