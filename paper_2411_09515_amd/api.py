@@ -20,7 +20,12 @@ PEAK_DTYPE = np.dtype([("index", np.uint32), ("y", np.float32), ("x", np.float32
 
 
 def _p(t):
-    return None if t is None else ctypes.c_void_p(t.data_ptr())
+    """Device pointer of a tensor handed to the C ABI (None for None); the
+    tensor must be a contiguous device tensor."""
+    if t is None:
+        return None
+    _need_device(t)
+    return ctypes.c_void_p(t.data_ptr())
 
 
 def _stream():
@@ -35,6 +40,56 @@ def _need_device(*tensors):
     for t in tensors:
         if t is not None and (not t.is_cuda or not t.is_contiguous()):
             raise ValueError("device tensors must be contiguous CUDA/HIP tensors")
+
+
+def _arg(t, name, dtypes, shape=None, min_numel=None):
+    """Check one tensor argument before anything is launched: dtype (one of
+    ``dtypes``), shape (a tuple, None for any extent) or a minimum size.  A
+    mismatch raises ValueError: a wrongly shaped buffer would otherwise be
+    read past its end by a kernel.  (Device and contiguity are checked when
+    the pointer is taken, ``_p``.)"""
+    if t is None:
+        return
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name}: expected a tensor, got {type(t).__name__}")
+    dtypes = dtypes if isinstance(dtypes, tuple) else (dtypes,)
+    if t.dtype not in dtypes:
+        raise ValueError(f"{name}: dtype {t.dtype}, expected {' or '.join(str(d) for d in dtypes)}")
+    if shape is not None:
+        if t.dim() != len(shape) or any(e is not None and int(a) != int(e) for a, e in zip(t.shape, shape)):
+            raise ValueError(f"{name}: shape {tuple(t.shape)}, expected {tuple(shape)}")
+    if min_numel is not None and t.numel() < min_numel:
+        raise ValueError(f"{name}: {t.numel()} elements, at least {min_numel} needed")
+
+
+def _profile_args(prof, F, nb, name="profile", keys=None):
+    for k in keys or ("mean", "std", "sem", "sum_w", "n_members", "n_iter", "converged"):
+        if k not in prof or prof[k] is None:
+            raise ValueError(f"{name}: missing '{k}'")
+        dt = torch.float64 if k in ("mean", "std", "sem", "sum_w") else torch.int32
+        _arg(prof[k], f"{name}['{k}']", dt, (F, nb))
+
+
+def _frames_arg(frames, geom, name="frames"):
+    if not isinstance(frames, torch.Tensor) or frames.dim() != 2:
+        raise ValueError(f"{name}: expected a [F, n_pix] tensor")
+    _arg(frames, name, torch.float32, (None, geom.n_pix))
+    return frames.shape[0]
+
+
+def _outputs_args(out, F, capacity, peak_capacity):
+    if out.get("kept_index") is not None or out.get("kept_value") is not None or out.get("n_kept") is not None:
+        _arg(out.get("kept_index"), "kept_index", (torch.int32, torch.uint32), (F, None))
+        _arg(out.get("kept_value"), "kept_value", torch.float32, (F, None))
+        _arg(out.get("n_kept"), "n_kept", torch.int64, (F,))
+        for k in ("kept_index", "kept_value"):
+            if out.get(k) is None or out[k].shape[1] < max(capacity, 1):
+                raise ValueError(f"{k}: needs [F, >= capacity] with capacity {capacity}")
+    if out.get("peaks") is not None or out.get("n_peaks") is not None:
+        _arg(out.get("peaks"), "peaks", torch.uint8, (F, None, B.PEAK_BYTES))
+        _arg(out.get("n_peaks"), "n_peaks", torch.int64, (F,))
+        if out.get("peaks") is None or out["peaks"].shape[1] < max(peak_capacity, 1):
+            raise ValueError(f"peaks: needs [F, >= peak_capacity, {B.PEAK_BYTES}]")
 
 
 @dataclass
@@ -140,8 +195,17 @@ class Geometry:
 
 def correct(raw, pedestal, gain, norm=None, out=None, n_invalid=None):
     """Raw Jungfrau words [F, N] uint16 -> corrected intensity [F, N] float32."""
-    _need_device(raw, pedestal, gain, norm, out, n_invalid)
+    if not isinstance(raw, torch.Tensor) or raw.dim() != 2:
+        raise ValueError("raw: expected a [F, N] tensor of 16-bit words")
     F, N = raw.shape
+    _arg(raw, "raw", (torch.uint16, torch.int16), (F, N))
+    _arg(pedestal, "pedestal", torch.float32, (3, N))
+    _arg(gain, "gain", torch.float32, (3, N))
+    if pedestal is None or gain is None:
+        raise ValueError("pedestal and gain are required")
+    _arg(norm, "norm", torch.float32, (N,))
+    _arg(out, "out", torch.float32, (F, N))
+    _arg(n_invalid, "n_invalid", torch.int64, (F,))
     if out is None:
         out = torch.empty((F, N), dtype=torch.float32, device=raw.device)
     if n_invalid is None:
@@ -165,16 +229,18 @@ def new_profile(n_frames, n_bins, device="cuda"):
 
 
 def profile_c(prof) -> B.Profile:
-    return B.Profile(*(prof[k].data_ptr() if prof.get(k) is not None else None
+    return B.Profile(*(_p(prof[k]).value if prof.get(k) is not None else None
                        for k in ("mean", "std", "sem", "sum_w", "n_members", "n_iter", "converged")))
 
 
 def sigma_clip(frames, geom: Geometry, params: Params, out=None, norm=None, mask=None, integrate_only=False):
     """Per-bin clipped profile of frames [F, N] float32 (corrected intensity)."""
-    _need_device(frames, norm, mask)
-    F = frames.shape[0]
+    F = _frames_arg(frames, geom)
+    _arg(norm, "norm", torch.float32, (geom.n_pix,))
+    _arg(mask, "mask", torch.uint8, (geom.n_pix,))
     if out is None:
         out = new_profile(F, geom.n_bins, frames.device)
+    _profile_args(out, F, geom.n_bins, "out")
     if norm is None and params.error_model != "azimuthal":
         norm = geom.norm
     fn = B.lib().ss_integrate_csr if integrate_only else B.lib().ss_sigma_clip
@@ -191,11 +257,12 @@ def sigma_clip_batches(batches, params: Params, outs=None):
     keep = []   # the ctypes structs must outlive the call
     arr = (B.ClipBatch * len(batches))()
     for i, ((frames, geom), out) in enumerate(zip(batches, outs)):
-        _need_device(frames)
+        F = _frames_arg(frames, geom, f"batches[{i}] frames")
+        _profile_args(out, F, geom.n_bins, f"outs[{i}]")
         csr, prof = geom.csr(), profile_c(out)
         keep += [csr, prof]
         norm = geom.norm if params.error_model != "azimuthal" else None
-        arr[i] = B.ClipBatch(frames.data_ptr(), None if norm is None else norm.data_ptr(), frames.shape[0],
+        arr[i] = B.ClipBatch(_p(frames).value, None if norm is None else _p(norm).value, frames.shape[0],
                              ctypes.addressof(csr), ctypes.addressof(prof))
     B.check("ss_sigma_clip_batches", B.lib().ss_sigma_clip_batches(arr, len(batches), ctypes.byref(params.c()),
                                                                    _stream()))
@@ -244,8 +311,8 @@ def integrate(frames, geom: Geometry, params: Params, out=None, norm=None, mask=
 
 def clip_features(frames, geom: Geometry, norm=None):
     """Surrogate inputs [F, nb, 19] (float32) and unclipped (n, mean, std) [F, nb, 3] (float64)."""
-    _need_device(frames, norm)
-    F = frames.shape[0]
+    F = _frames_arg(frames, geom)
+    _arg(norm, "norm", torch.float32, (geom.n_pix,))
     feats = torch.empty((F, geom.n_bins, B.SS_MLP_IN), dtype=torch.float32, device=frames.device)
     stats0 = torch.empty((F, geom.n_bins, 3), dtype=torch.float64, device=frames.device)
     B.check("ss_clip_features", B.lib().ss_clip_features(_p(frames), _p(norm), None, F, ctypes.byref(geom.csr()),
@@ -255,6 +322,8 @@ def clip_features(frames, geom: Geometry, norm=None):
 
 def surrogate_targets(stats0, profile):
     """Training targets [n, 2] and use flags [n] from unclipped stats and a converged clip."""
+    _arg(stats0, "stats0", torch.float64, (None, None, 3))
+    _profile_args(profile, stats0.shape[0], stats0.shape[1])
     n = stats0.numel() // 3
     target = torch.empty((n, 2), dtype=torch.float32, device=stats0.device)
     use = torch.empty(n, dtype=torch.uint8, device=stats0.device)
@@ -299,7 +368,7 @@ class Surrogate:
         return self.w16.cpu().numpy().view(np.float16).astype(np.float64)
 
     def forward(self, x):
-        _need_device(x)
+        _arg(x, "x", torch.float32, (None, B.SS_MLP_IN))
         n = x.shape[0]
         y = torch.empty((n, B.SS_MLP_OUT), dtype=torch.float32, device=x.device)
         B.check("ss_mlp_forward", B.lib().ss_mlp_forward(_p(self.w16), _p(x), n, _p(y), _stream()))
@@ -307,8 +376,10 @@ class Surrogate:
 
     def gradient(self, x, target, use=None):
         """Loss and gradient (into self.loss / self.grad) on samples x [n, 19]."""
-        _need_device(x, target, use)
+        _arg(x, "x", torch.float32, (None, B.SS_MLP_IN))
         n = x.shape[0]
+        _arg(target, "target", torch.float32, (n, B.SS_MLP_OUT))
+        _arg(use, "use", torch.uint8, (n,))
         need = int(B.lib().ss_mlp_grad_workspace(n))
         if self._ws is None or self._ws.numel() < need:
             self._ws = torch.empty(need, dtype=torch.uint8, device=x.device)
@@ -341,10 +412,12 @@ def sigma_clip_surrogate(frames, geom: Geometry, params: Params, model: Surrogat
                          state=None, norm=None):
     """The clip warm-started by the surrogate; ``state`` [F, nb] int32 receives
     1 (accepted), 0 (no prediction) or -1 (refused, clipped again from scratch)."""
-    _need_device(frames, norm, state)
-    F = frames.shape[0]
+    F = _frames_arg(frames, geom)
+    _arg(norm, "norm", torch.float32, (geom.n_pix,))
+    _arg(state, "state", torch.int32, (F, geom.n_bins))
     if out is None:
         out = new_profile(F, geom.n_bins, frames.device)
+    _profile_args(out, F, geom.n_bins, "out")
     if state is None:
         state = torch.empty((F, geom.n_bins), dtype=torch.int32, device=frames.device)
     B.check("ss_sigma_clip_surrogate",
@@ -367,8 +440,10 @@ def new_workspace(n_frames, geom: Geometry, device="cuda"):
 def classify(frames, geom: Geometry, profile, params: Params, capacity=0, peak_capacity=0, keep=True,
              peaks=True, mask=None, workspace=None, out=None):
     """Sparsification and/or peak finding of frames [F, N] against a profile."""
-    _need_device(frames, mask, workspace)
-    F = frames.shape[0]
+    F = _frames_arg(frames, geom)
+    _arg(mask, "mask", torch.uint8, (geom.n_pix,))
+    _arg(workspace, "workspace", torch.uint8, min_numel=workspace_bytes(F, geom.n_pix, geom.n_bins))
+    _profile_args(profile, F, geom.n_bins, keys=("mean", "std", "n_members"))
     dev = frames.device
     if workspace is None:
         workspace = new_workspace(F, geom, dev)
@@ -381,6 +456,7 @@ def classify(frames, geom: Geometry, profile, params: Params, capacity=0, peak_c
         if peaks:
             out["peaks"] = torch.empty((F, max(peak_capacity, 1), B.PEAK_BYTES), dtype=torch.uint8, device=dev)
             out["n_peaks"] = torch.empty(F, dtype=torch.int64, device=dev)
+    _outputs_args(out, F, capacity if keep else 0, peak_capacity if peaks else 0)
     args = (_p(frames), _p(mask), F, geom.height, geom.width, ctypes.byref(geom.radial()),
             ctypes.byref(profile_c(profile)), ctypes.byref(params.c()))
     B.check("ss_classify", B.lib().ss_classify(
@@ -394,8 +470,10 @@ def classify_noalloc(frames, geom: Geometry, profile, params: Params, out, capac
     """``classify`` through ss_classify_noalloc: the library's own device array
     serves as workspace (nothing is allocated); ``out`` holds the caller's
     output tensors (kept_index, kept_value, n_kept, peaks, n_peaks)."""
-    _need_device(frames, mask, *out.values())
-    F = frames.shape[0]
+    F = _frames_arg(frames, geom)
+    _arg(mask, "mask", torch.uint8, (geom.n_pix,))
+    _profile_args(profile, F, geom.n_bins, keys=("mean", "std", "n_members"))
+    _outputs_args(out, F, capacity, peak_capacity)
     args = (_p(frames), _p(mask), F, geom.height, geom.width, ctypes.byref(geom.radial()),
             ctypes.byref(profile_c(profile)), ctypes.byref(params.c()))
     B.check("ss_classify_noalloc", B.lib().ss_classify_noalloc(
@@ -405,8 +483,10 @@ def classify_noalloc(frames, geom: Geometry, profile, params: Params, out, capac
 
 
 def compress(frames, geom, profile, params, capacity, mask=None, workspace=None):
-    _need_device(frames, mask, workspace)
-    F = frames.shape[0]
+    F = _frames_arg(frames, geom)
+    _arg(mask, "mask", torch.uint8, (geom.n_pix,))
+    _arg(workspace, "workspace", torch.uint8, min_numel=workspace_bytes(F, geom.n_pix, geom.n_bins))
+    _profile_args(profile, F, geom.n_bins, keys=("mean", "std", "n_members"))
     dev = frames.device
     if workspace is None:
         workspace = new_workspace(F, geom, dev)
@@ -421,8 +501,10 @@ def compress(frames, geom, profile, params, capacity, mask=None, workspace=None)
 
 
 def peakfind(frames, geom, profile, params, peak_capacity, mask=None, workspace=None):
-    _need_device(frames, mask, workspace)
-    F = frames.shape[0]
+    F = _frames_arg(frames, geom)
+    _arg(mask, "mask", torch.uint8, (geom.n_pix,))
+    _arg(workspace, "workspace", torch.uint8, min_numel=workspace_bytes(F, geom.n_pix, geom.n_bins))
+    _profile_args(profile, F, geom.n_bins, keys=("mean", "std", "n_members"))
     dev = frames.device
     if workspace is None:
         workspace = new_workspace(F, geom, dev)
@@ -448,8 +530,14 @@ def densify(sparse, geom: Geometry, profile, n_frames=None, noise=None, mask=Non
     ref = profile["mean"]
     F = int(n_frames if sparse is None else sparse["n_kept"].shape[0])
     dev = ref.device
-    _need_device(mask, out, workspace, ref, profile["std"], profile["n_members"],
-                 *(() if sparse is None else (sparse["kept_index"], sparse["kept_value"], sparse["n_kept"])))
+    _profile_args(profile, F, geom.n_bins, keys=("mean", "std", "n_members"))
+    _arg(mask, "mask", torch.uint8, (geom.n_pix,))
+    _arg(out, "out", torch.float32, (F, geom.n_pix))
+    _arg(workspace, "workspace", torch.uint8, min_numel=int(B.lib().ss_densify_workspace(F, geom.n_bins)))
+    if sparse is not None:
+        _arg(sparse["kept_index"], "kept_index", (torch.int32, torch.uint32), (F, None))
+        _arg(sparse["kept_value"], "kept_value", torch.float32, (F, sparse["kept_index"].shape[1]))
+        _arg(sparse["n_kept"], "n_kept", torch.int64, (F,))
     if out is None:
         out = torch.empty((F, geom.n_pix), dtype=torch.float32, device=dev)
     if workspace is None:
@@ -474,8 +562,11 @@ def new_veto_counters(device="cuda"):
 
 def veto(n_peaks, threshold, n_kept=None, counters=None, hit=None):
     """Peak-count veto (Sec. 4): hit [F] uint8 and the accumulated counters."""
-    _need_device(n_peaks, n_kept, counters, hit)
+    _arg(n_peaks, "n_peaks", torch.int64, (None,))
     F = n_peaks.numel()
+    _arg(n_kept, "n_kept", torch.int64, (F,))
+    _arg(counters, "counters", torch.int64, (B.SS_VETO_COUNTERS,))
+    _arg(hit, "hit", torch.uint8, (F,))
     if counters is None:
         counters = new_veto_counters(n_peaks.device)
     if hit is None:
@@ -506,7 +597,13 @@ def pack_results(out, capacity, peak_capacity, packed=None):
                       peaks=torch.empty((max(F * peak_capacity, 1), B.PEAK_BYTES), dtype=torch.uint8, device=dev))
     keep = out.get("n_kept") is not None
     pk = out.get("n_peaks") is not None
-    _need_device(*(v for v in out.values()), *(v for v in packed.values()))
+    _outputs_args(out, F, capacity if keep else 0, peak_capacity if pk else 0)
+    _arg(packed["offsets"], "offsets", torch.int64, min_numel=2 * (F + 1))
+    if keep:
+        _arg(packed["index"], "packed index", (torch.int32, torch.uint32), min_numel=F * capacity)
+        _arg(packed["value"], "packed value", torch.float32, min_numel=F * capacity)
+    if pk:
+        _arg(packed["peaks"], "packed peaks", torch.uint8, min_numel=F * peak_capacity * B.PEAK_BYTES)
     B.check("ss_pack_results", B.lib().ss_pack_results(
         _p(out.get("kept_index")) if keep else None, _p(out.get("kept_value")) if keep else None, capacity,
         _p(out.get("n_kept")) if keep else None, _p(out.get("peaks")) if pk else None, peak_capacity,

@@ -230,3 +230,48 @@ def test_classify_noalloc_refuses_oversize_before_any_device_call():
     assert L.ss_classify_noalloc(*none) == B.SS_OK
     assert L.ss_classify_noalloc(None, None, 1, 4, 4, None, ref(prof), ref(p), None, None, 0, None, None, 0,
                                  None, None) == B.SS_EINVAL
+
+
+def test_wrappers_refuse_bad_dtypes_and_shapes_before_launch():
+    """Every torch-facing wrapper checks dtype and shape against the geometry
+    and the frame count and raises ValueError before any launch (a wrongly
+    shaped buffer would be read past its end on the device)."""
+    import torch
+    g = synth.SMALL
+    geo = api.Geometry.from_scene(g, synth.stripe_mask(g), None, "cpu")
+    N, nb = geo.n_pix, geo.n_bins
+    p = api.Params()
+    f32 = torch.zeros((2, N), dtype=torch.float32)
+
+    def bad(fn, *a, what, **kw):
+        with pytest.raises(ValueError) as e:
+            fn(*a, **kw)
+        assert what in str(e.value), str(e.value)
+
+    raw = torch.zeros((2, N), dtype=torch.uint16)
+    ped = torch.zeros((3, N), dtype=torch.float32)
+    bad(api.correct, raw.to(torch.int32), ped, ped, what="raw: dtype")
+    bad(api.correct, raw, ped[:2], ped, what="pedestal: shape")
+    bad(api.correct, raw, ped, ped.double(), what="gain: dtype")
+    bad(api.correct, raw, ped, ped, torch.zeros(N - 1), what="norm: shape")
+    bad(api.correct, raw, ped, ped, what="device")           # right types, host memory
+    bad(api.sigma_clip, f32.double(), geo, p, what="frames: dtype")
+    bad(api.sigma_clip, f32[:, :-1].contiguous(), geo, p, what="frames: shape")
+    bad(api.sigma_clip, f32, geo, p, mask=torch.zeros(N, dtype=torch.bool), what="mask: dtype")
+    prof = api.new_profile(2, nb, "cpu")
+    prof["n_iter"] = prof["n_iter"].long()
+    bad(api.sigma_clip, f32, geo, p, out=prof, what="out['n_iter']: dtype")
+    prof = api.new_profile(2, nb - 1, "cpu")
+    bad(api.classify, f32, geo, prof, p, capacity=8, what="profile['mean']: shape")
+    prof = api.new_profile(2, nb, "cpu")
+    bad(api.classify, f32, geo, prof, p, capacity=8, workspace=torch.zeros(16, dtype=torch.uint8),
+        what="workspace")
+    out = dict(kept_index=torch.zeros((2, 4), dtype=torch.int32), kept_value=torch.zeros((2, 4)),
+               n_kept=torch.zeros(2, dtype=torch.int64), peaks=torch.zeros((2, 4, B.PEAK_BYTES), dtype=torch.uint8),
+               n_peaks=torch.zeros(2, dtype=torch.int64))
+    bad(api.classify_noalloc, f32, geo, prof, p, out, 8, 4, what="capacity")
+    bad(api.veto, torch.zeros(3, dtype=torch.int32), 2, what="n_peaks: dtype")
+    bad(api.veto, torch.zeros(3, dtype=torch.int64), 2, counters=torch.zeros(5, dtype=torch.int64),
+        what="counters: shape")
+    model_x = torch.zeros((5, B.SS_MLP_IN + 1))
+    bad(api.Surrogate.forward, None, model_x, what="x: shape")
