@@ -373,22 +373,84 @@ def cpu_baseline(raw, budget_s=20.0, pool_cores=0):
     return out
 
 
-def algorithmic_bytes(geo, n_frames, n_pix_valid, n_kept, n_peaks):
-    """Bytes each kernel must move once per launch for a batch of n_frames.
+PROFILE_BYTES_PER_BIN = 4 * 8 + 3 * 4   # mean, std, sem, sum_w (float64) + members, passes, converged
+
+
+def method_bytes(geo, n_frames, n_kept, n_peaks):
+    """What the method must move once for a batch of n_frames sharing one
+    geometry (the path's algorithmic bytes): raw words 2 B per pixel and
+    frame, the calibration each pixel selects (pedestal and gain of its gain
+    level, the normalisation folded in: 8 B per pixel, once), the CSR (index
+    and weight, 8 B per entry, once) and the outputs (profile, kept entries
+    8 B, peaks 20 B).  ``clip`` is the share a clip that reads the raw words
+    itself would move: raw + calibration + CSR + profile."""
+    n_pix, nb = geo.n_pix, geo.n_bins
+    raw, calib, csr = 2 * n_pix * n_frames, 8 * n_pix, 8 * geo.nnz
+    profile = PROFILE_BYTES_PER_BIN * nb * n_frames
+    return dict(path=raw + calib + csr + profile + 8 * n_kept + 20 * n_peaks,
+                clip=raw + calib + csr + profile)
+
+
+def built_bytes(geo, n_frames, n_pix_valid, n_kept, n_peaks):
+    """Bytes each C-ABI call moves once per launch as built (the corrected
+    float32 frame is materialised between the stages).
 
     correct : raw words 2 B/px/frame + corrected frame 4 B/px/frame + level-0
               pedestal, gain and norm once (12 B/px)
     clip    : CSR index + weight once (8 B/entry) + each unmasked pixel of
-              each frame once (4 B) + profile (48 B/bin/frame)
+              each frame once (4 B) + profile
     classify: frame 4 B/px/frame + radial code once (4 B/px) + kept entries
               (8 B) and peaks (20 B)
     """
     n_pix = geo.n_pix
     return dict(
         correct=(2 + 4) * n_pix * n_frames + 12 * n_pix,
-        clip=8 * geo.nnz + 4 * n_pix_valid * n_frames + 48 * geo.n_bins * n_frames,
+        clip=8 * geo.nnz + 4 * n_pix_valid * n_frames + PROFILE_BYTES_PER_BIN * geo.n_bins * n_frames,
         classify=4 * n_pix * n_frames + 4 * n_pix + 8 * n_kept + 20 * n_peaks,
     )
+
+
+# VALU issue peak: 256 CUs x 4 SIMDs, a wave64 VALU instruction occupying a
+# 16-lane SIMD for 4 cycles, at 2.4 GHz: 256 x 4 x 2.4e9 / 4 = 614.4e9
+# wave-instructions per second.
+VALU_PEAK_GINSTR = 256 * 4 * 2.4 / 4
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "clip_jungfrau4m_64frames_counters.md")
+
+
+def measured_valu(stage, n_frames):
+    """VALU wave-instructions per call of a stage from the committed counter
+    summary (the rows of its kernels), or None when it is missing, taken on
+    another batch size or on other sources."""
+    import hashlib
+    if n_frames != 64 or not os.path.exists(COUNTERS_FILE):
+        return None
+    for line in open(COUNTERS_FILE):
+        f = dict(kv.split("=", 1) for kv in line.split() if "=" in kv)
+        if line.strip().startswith("valu ") and f.get("stage") == stage:
+            h = hashlib.sha256()
+            for src in f["sources"].split(","):
+                h.update(open(os.path.join(ROOT, src), "rb").read())
+            return float(f["instructions"]) if h.hexdigest()[:16] == f["sha256_16"] else None
+    return None
+
+
+def device_copy_gbs(torch, dev, nbytes=1 << 30, reps=10):
+    """Achievable HBM rate of a plain device-to-device copy (bytes read +
+    written per second), measured in the same run."""
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    stream = torch.cuda.current_stream()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(reps):
+        dst.copy_(src)
+    b.record(stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    del src, dst
+    return round(2 * nbytes / (ms * 1e-3) / 1e9, 1)
 
 
 STAGE_KERNELS = {
@@ -415,6 +477,17 @@ def measured_traffic(stage, n_frames):
                 h.update(open(os.path.join(ROOT, src), "rb").read())
             return int(f["bytes"]) if h.hexdigest()[:16] == f["sha256_16"] else None
     return None
+
+
+def valu_limit(stage, ms, n_frames):
+    """VALU issue of a stage's launch against the issue peak, from the
+    committed counters (None when they do not cover the current sources)."""
+    instr = measured_valu(stage, n_frames)
+    if instr is None:
+        return None
+    rate = instr / (ms * 1e-3) / 1e9
+    return {"kind": "valu issue", "ginstr_per_s": round(rate, 1), "peak_ginstr_per_s": VALU_PEAK_GINSTR,
+            "frac": round(rate / VALU_PEAK_GINSTR, 3)}
 
 
 def main():
@@ -499,9 +572,9 @@ def main():
     n_kept = int(pipe.out["n_kept"].sum())
     n_peaks = int(pipe.out["n_peaks"].sum())
     n_valid = int((mask.reshape(-1) == 0).sum())
-    alg = algorithmic_bytes(geo, F, n_valid, n_kept, n_peaks)
+    built = built_bytes(geo, F, n_valid, n_kept, n_peaks)
+    meth = method_bytes(geo, F, n_kept, n_peaks)
     dom = max(stage, key=stage.get)
-    achieved = alg[dom] / (stage[dom] * 1e-3) / 1e9
     print(f"# stages ms: {stage}; kept {n_kept}, peaks {n_peaks}", file=sys.stderr, flush=True)
 
     if args.copy_calibration:
@@ -511,6 +584,8 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    copy_gbs = device_copy_gbs(torch, dev)
+    print(f"# device copy: {copy_gbs} GB/s", file=sys.stderr, flush=True)
 
     # single-frame latency: one raw frame through the whole path, per call
     one = api.Pipeline(geo, params, 1, pipe.pedestal, pipe.gain, kept_capacity=1 << 16, peak_capacity=1 << 12,
@@ -592,19 +667,28 @@ def main():
         "roofline": {
             "kernel": STAGE_KERNELS[dom],
             "bound": "hbm",
-            "achieved": round(achieved, 1),
+            "achieved": round(meth[dom] / (stage[dom] * 1e-3) / 1e9, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "frac": round(meth[dom] / (stage[dom] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
             "traffic": measured_traffic(dom, F),
-            "algorithmic_bytes_per_launch": alg[dom],
+            "algorithmic_bytes_per_launch": meth[dom],
+            "algorithmic_bytes_model": "raw 2 B/px/frame + selected calibration 8 B/px + CSR 8 B/entry + "
+                                       f"profile {PROFILE_BYTES_PER_BIN} B/bin/frame",
             "launch_ms": round(stage[dom], 4),
+            "device_copy_gbs": copy_gbs,
+            "nearer_limit": valu_limit(dom, stage[dom], F),
         },
-        "stages_roofline": {
-            k: {"algorithmic_bytes": alg[k], "achieved_gbs": round(alg[k] / (stage[k] * 1e-3) / 1e9, 1),
-                "traffic": measured_traffic(k, F)} for k in stage
+        "path": {
+            "algorithmic_bytes_per_step": meth["path"],
+            "achieved_gbs": round(meth["path"] / (ms_per_step * 1e-3) / 1e9, 1),
+            "frac": round(meth["path"] / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "frac_of_device_copy": round(meth["path"] / (ms_per_step * 1e-3) / 1e9 / copy_gbs, 4),
         },
-        "path_hbm_frac": round(sum(alg.values()) / (sum(stage.values()) * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "stages_as_built": {
+            k: {"bytes": built[k], "achieved_gbs": round(built[k] / (stage[k] * 1e-3) / 1e9, 1),
+                "traffic": measured_traffic(k, F), "valu_issue": valu_limit(k, stage[k], F)} for k in stage
+        },
         "surrogate_vs_plain": sur,
         "batched_uneven": batched,
         "serving": served,
