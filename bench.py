@@ -217,11 +217,19 @@ def surrogate_vs_plain(api, torch, geo, pipe, train_raw, frames, steps, reps=5):
     X, T, U = torch.cat(X), torch.cat(T), torch.cat(U)
     torch.cuda.synchronize()
     t_data = time.perf_counter() - t0
-    model = api.Surrogate(seed=1, device=dev)
-    t0 = time.perf_counter()
-    hist = model.train(X, T, U, steps=steps, batch=16384, lr=2e-3, log_every=max(1, steps // 4))
-    torch.cuda.synchronize()
-    t_train = time.perf_counter() - t0
+    # final training loss against the number of training frames (the first
+    # n frames' samples; the last model is the one used below)
+    per_frame = X.shape[0] // max(1, train_raw.shape[0] // F * F)
+    loss_vs_frames = {}
+    for n in sorted({max(F, train_raw.shape[0] // 4), max(F, train_raw.shape[0] // 2), train_raw.shape[0]}):
+        k = min(X.shape[0], n * per_frame)
+        model = api.Surrogate(seed=1, device=dev)
+        t0 = time.perf_counter()
+        hist = model.train(X[:k].contiguous(), T[:k].contiguous(), U[:k].contiguous(), steps=steps, batch=16384,
+                           lr=2e-3, log_every=max(1, steps // 4))
+        torch.cuda.synchronize()
+        t_train = time.perf_counter() - t0
+        loss_vs_frames[n] = round(hist[-1], 5)
 
     stream = torch.cuda.current_stream()
 
@@ -242,6 +250,28 @@ def surrogate_vs_plain(api, torch, geo, pipe, train_raw, frames, steps, reps=5):
     sur_ms, _ = timed(lambda: api.sigma_clip_surrogate(frames, geo, conv, model, out=sur_out, widen=0.1, state=state))
     sur = sur_out
     plain5_ms, _ = timed(lambda: api.sigma_clip(frames, geo, api.Params(cutoff=3.0, max_iter=5)))
+    # the same verified warm start with given predictions: the plain clip's own
+    # converged profile (a perfect predictor: the most any predictor can save)
+    # and the previous frame's profile (a predictor that costs nothing)
+    warm = {}
+    prev = {k: torch.roll(plain[k], 1, dims=0).contiguous() for k in ("mean", "std")}
+    w_out = api.new_profile(frames.shape[0], geo.n_bins, dev)
+    w_state = torch.zeros_like(state)
+    for name, (pmh, psh), widen in (("perfect_widen_0", (plain["mean"], plain["std"]), 0.0),
+                                    ("perfect_widen_0.1", (plain["mean"], plain["std"]), 0.1),
+                                    ("previous_frame", (prev["mean"], prev["std"]), 0.1)):
+        ms, _ = timed(lambda: api.sigma_clip_warm(frames, geo, conv, pmh, psh, out=w_out, widen=widen, state=w_state))
+        ws = w_state.cpu().numpy()
+        acc = ws == 1
+        pw = (w_out["n_iter"] + w_out["converged"]).cpu().numpy()
+        pp = (plain["n_iter"] + plain["converged"]).cpu().numpy()
+        same = np.all(np.abs(w_out["mean"].cpu().numpy() - plain["mean"].cpu().numpy())
+                      <= 1e-5 * np.abs(plain["mean"].cpu().numpy()) + 1e-12)
+        warm[name] = {"ms": round(ms, 4), "speedup_vs_plain": round(plain_ms / ms, 3),
+                      "accepted_frac": round(float(acc.mean()), 4), "refused_frac": round(float((ws == -1).mean()), 4),
+                      "passes_accepted": round(float(pw[acc].mean()), 3) if acc.any() else None,
+                      "passes_plain_same_bins": round(float(pp[acc].mean()), 3) if acc.any() else None,
+                      "means_equal_plain": bool(same)}
     pm, sm = plain["mean"].cpu().numpy(), sur["mean"].cpu().numpy()
     ps, ss = plain["std"].cpu().numpy(), sur["std"].cpu().numpy()
     same_n = plain["n_members"].cpu().numpy() == sur["n_members"].cpu().numpy()
@@ -268,6 +298,8 @@ def surrogate_vs_plain(api, torch, geo, pipe, train_raw, frames, steps, reps=5):
         "accuracy_vs_plain": {"bins_within_tolerance": round(float(tol_ok.mean()), 6),
                               "same_member_count": round(float(same_n.mean()), 6),
                               "tolerance": "|x - x_plain| <= 1e-5 |x_plain| + 1e-7 |mean_plain|"},
+        "warm_start_given_predictions": warm,
+        "final_loss_vs_training_frames": loss_vs_frames,
         "training": {"frames": int(train_raw.shape[0]), "samples_used": int(U.sum().item()),
                      "steps": steps, "batch": 16384, "loss": [round(h, 5) for h in hist],
                      "data_s": round(t_data, 2), "train_s": round(t_train, 2)},
@@ -499,7 +531,7 @@ def main():
     ap.add_argument("--latency-iters", type=int, default=200)
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--train-frames", type=int, default=128,
+    ap.add_argument("--train-frames", type=int, default=256,
                     help="surrogate training frames (0 skips the surrogate comparison)")
     ap.add_argument("--train-steps", type=int, default=3000)
     ap.add_argument("--no-batched", action="store_true", help="skip the mixed-detector batch")

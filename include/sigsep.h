@@ -548,6 +548,23 @@ int ss_sigma_clip_surrogate(const float *frames, const float *norm, const uint8_
                             const uint16_t *w16, float widen, const ss_profile *out,
                             int32_t *accepted, hipStream_t stream);
 
+/* ss_sigma_clip_warm -- the verified warm start of ss_sigma_clip_surrogate
+ * with the prediction given instead of computed: pred_mean, pred_std [dev]
+ * double [n_frames][n_bins] are each bin's predicted converged mean and std
+ * (for instance the previous frame's profile in a stream of similar frames,
+ * or any external predictor).  Pass 0 also removes the members outside
+ * pred_mean +- cutoff (1 + widen) pred_std; acceptance, refusal (a second,
+ * plain launch) and the bins without a warm start (fewer than 64 members,
+ * zero spread, a predicted interval reaching zero, or a prediction that is
+ * not positive) are exactly those of ss_sigma_clip_surrogate, so every bin
+ * ends on the plain clip's fixed point or is clipped plainly.
+ * Requirements and errors as ss_sigma_clip_surrogate (pred_mean and
+ * pred_std replace w16). */
+int ss_sigma_clip_warm(const float *frames, const float *norm, const uint8_t *mask,
+                       int32_t n_frames, const ss_csr *csr, const ss_params *params,
+                       const double *pred_mean, const double *pred_std, float widen,
+                       const ss_profile *out, int32_t *accepted, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

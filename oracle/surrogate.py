@@ -239,31 +239,34 @@ def warm_bin(v, omega, mean_hat, std_hat, cutoff, max_iter, widen):
     return state, keep, n_iter, converged
 
 
-def surrogate_clip(frame, norm, csr, p, mask=None, cutoff=3.0, max_iter=32, widen=0.1):
-    """Profile of one frame from the warm-started clip, plain clip as fallback.
+def warm_clip(frame, norm, csr, mean_hat, std_hat, mask=None, cutoff=3.0, max_iter=32, widen=0.1, stats0=None):
+    """Profile of one frame from the clip warm-started by given per-bin
+    predictions of the converged mean and std (``mean_hat``, ``std_hat``
+    [n_bins]: the network's, or any other predictor's), plain clip as the
+    fallback.  A bin gets a warm start when it has at least MIN_MEMBERS
+    members, a positive unclipped std, a positive predicted std and a
+    predicted interval mean_hat - cutoff (1 + widen) std_hat above zero.
 
     Returns the dict of ``stats.sigma_clip`` plus ``state`` per bin (1 warm
-    start accepted, 0 no prediction, -1 clipped again from scratch).
+    start accepted, 0 no warm start, -1 clipped again from scratch).
     """
     frame = np.asarray(frame).reshape(-1)
     normf = None if norm is None else np.asarray(norm).reshape(-1)
     maskf = None if mask is None else np.asarray(mask).reshape(-1)
     plain = S.sigma_clip(frame, normf, csr, maskf, cutoff, max_iter)
-    X, st = features(frame, normf, csr, maskf)
-    y = forward(p, X)
+    st = features(frame, normf, csr, maskf)[1] if stats0 is None else stats0
     out = {k: np.array(val, copy=True) for k, val in plain.items()}
     out["state"] = np.zeros(csr.n_bins, dtype=np.int64)
     for r in range(csr.n_bins):
         n0, m0, s0 = st[r]
         if n0 < 2 or not (s0 > 0) or max_iter < 1:
             continue
+        mh, sh = float(mean_hat[r]), float(std_hat[r])
+        if n0 < MIN_MEMBERS or not (sh > 0) or not (mh - cutoff * (1.0 + widen) * sh > 0):
+            continue
         mb = S.bin_members(frame, normf, csr, r, maskf)
         v, omega = mb.v, mb.omega
-        mean_hat = m0 + y[r, 0] * s0
-        std_hat = s0 * math.exp(y[r, 1])
-        if n0 < MIN_MEMBERS or not (mean_hat - cutoff * (1.0 + widen) * std_hat > 0):
-            continue
-        state, keep, n_iter, conv = warm_bin(v, omega, mean_hat, std_hat, cutoff, max_iter, widen)
+        state, keep, n_iter, conv = warm_bin(v, omega, mh, sh, cutoff, max_iter, widen)
         out["state"][r] = state
         if state != 1:
             continue
@@ -272,3 +275,17 @@ def surrogate_clip(frame, norm, csr, p, mask=None, cutoff=3.0, max_iter=32, wide
         out["sum_w"][r], out["n_members"][r] = m["Omega"], m["n"]
         out["n_iter"][r], out["converged"][r] = n_iter, conv
     return out
+
+
+def surrogate_clip(frame, norm, csr, p, mask=None, cutoff=3.0, max_iter=32, widen=0.1):
+    """Profile of one frame from the warm-started clip, the network's
+    prediction from the bin's features (``warm_clip``), plain clip as the
+    fallback."""
+    frame = np.asarray(frame).reshape(-1)
+    normf = None if norm is None else np.asarray(norm).reshape(-1)
+    maskf = None if mask is None else np.asarray(mask).reshape(-1)
+    X, st = features(frame, normf, csr, maskf)
+    y = forward(p, X)
+    mean_hat = st[:, 1] + y[:, 0] * st[:, 2]
+    std_hat = st[:, 2] * np.exp(y[:, 1])
+    return warm_clip(frame, normf, csr, mean_hat, std_hat, maskf, cutoff, max_iter, widen, stats0=st)

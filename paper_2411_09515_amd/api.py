@@ -427,6 +427,27 @@ def sigma_clip_surrogate(frames, geom: Geometry, params: Params, model: Surrogat
     return out, state
 
 
+def sigma_clip_warm(frames, geom: Geometry, params: Params, pred_mean, pred_std, out=None, widen=0.1, state=None):
+    """The clip warm-started from given per-bin predictions of the converged
+    mean and std (float64 [F, nb], e.g. the previous frame's profile), with
+    the surrogate's verification; ``state`` [F, nb] int32 receives 1
+    (accepted), 0 (no warm start) or -1 (refused, clipped again)."""
+    F = _frames_arg(frames, geom)
+    _arg(pred_mean, "pred_mean", torch.float64, (F, geom.n_bins))
+    _arg(pred_std, "pred_std", torch.float64, (F, geom.n_bins))
+    _arg(state, "state", torch.int32, (F, geom.n_bins))
+    if out is None:
+        out = new_profile(F, geom.n_bins, frames.device)
+    _profile_args(out, F, geom.n_bins, "out")
+    if state is None:
+        state = torch.empty((F, geom.n_bins), dtype=torch.int32, device=frames.device)
+    B.check("ss_sigma_clip_warm",
+            B.lib().ss_sigma_clip_warm(_p(frames), None, None, F, ctypes.byref(geom.csr()), ctypes.byref(params.c()),
+                                       _p(pred_mean), _p(pred_std), widen, ctypes.byref(profile_c(out)), _p(state),
+                                       _stream()))
+    return out, state
+
+
 # -- classification ----------------------------------------------------------------------
 
 def workspace_bytes(n_frames, n_pix, n_bins) -> int:

@@ -39,7 +39,7 @@ EXPORTED = (
     "ss_integrate_csr", "ss_sigma_clip", "ss_classify_workspace", "ss_classify", "ss_classify_noalloc",
     "ss_compress", "ss_peakfind",
     "ss_clip_features", "ss_surrogate_targets", "ss_mlp_forward", "ss_mlp_grad_workspace", "ss_mlp_grad",
-    "ss_mlp_adam", "ss_sigma_clip_surrogate", "ss_sigma_clip_batches",
+    "ss_mlp_adam", "ss_sigma_clip_surrogate", "ss_sigma_clip_warm", "ss_sigma_clip_batches",
     "ss_densify_workspace", "ss_densify", "ss_veto", "ss_pack_results",
 )
 
@@ -150,6 +150,8 @@ def lib():
         L.ss_mlp_adam.argtypes = [vp, vp, vp, vp, i32, f32, f32, f32, f32, vp, vp]
         L.ss_sigma_clip_surrogate.restype = ctypes.c_int
         L.ss_sigma_clip_surrogate.argtypes = [vp, vp, vp, i32, P(Csr), P(Params), vp, f32, P(Profile), vp, vp]
+        L.ss_sigma_clip_warm.restype = ctypes.c_int
+        L.ss_sigma_clip_warm.argtypes = [vp, vp, vp, i32, P(Csr), P(Params), vp, vp, f32, P(Profile), vp, vp]
         L.ss_sigma_clip_batches.restype = ctypes.c_int
         L.ss_sigma_clip_batches.argtypes = [vp, i32, P(Params), vp]
         L.ss_densify_workspace.restype = sz

@@ -67,11 +67,14 @@ struct ClipArgs {
     double widen;           // widening of the predicted bounds, surrogate mode
     int32_t *accepted;      // [F][nb] states, surrogate mode (1 accepted, 0 none, -1 refused)
     const int32_t *redo;    // plain launch after the surrogate: process groups with state -1 only
+    const double *pred_mean;  // [F][nb] given predictions, warm mode
+    const double *pred_std;
 };
 
 // What k_clip_regs computes: the clipped profile, the surrogate's features
-// only, or the clipped profile with the verified surrogate first.
-enum { MODE_CLIP = 0, MODE_FEATURES = 1, MODE_SURROGATE = 2 };
+// only, the clipped profile with the verified surrogate first, or the
+// clipped profile warm-started from given predictions (same verification).
+enum { MODE_CLIP = 0, MODE_FEATURES = 1, MODE_SURROGATE = 2, MODE_WARM = 3 };
 
 struct Stats {
     double mean, std, sem, pstd, psem;
@@ -358,6 +361,29 @@ __device__ inline void wave_sync() {
 
 #define SS_V(f, e) vp[f][(e) >> 1][(e) & 1]
 
+__device__ inline double u_mean(const Surrogate &u, double y0) { return u.m0 + y0 * u.s0; }
+__device__ inline double u_std(const Surrogate &u, double y1) { return u.s0 * exp(y1); }
+
+// The warm start of a frame's clip from a predicted converged (mean, std):
+// pass 0 also removes the members outside mean_hat +- cutoff (1 + widen)
+// std_hat.  No warm start in small bins or where the predicted interval
+// reaches zero (low counts): their clip can have several fixed points (for
+// low counts one per photon-number cluster), and a warm start could settle
+// on another one than the plain clip.
+__device__ inline void warm_start(const ClipArgs &a, Surrogate &u, PassCtl &ctl, double mean_hat, double std_hat) {
+    u.mean_hat = mean_hat;
+    u.std_hat = std_hat;
+    u.half = a.cutoff * (1.0 + a.widen) * u.std_hat;
+    u.warm = u.on && u.n0 >= double(kWarmMinMembers) && u.s0 > 0.0 && ctl.go && u.half > 0.0 &&
+             u.mean_hat - u.half > 0.0;
+    if (u.warm) {
+        // pass 0 keeps the members within both its own bounds and
+        // |v - mean_hat| <= half, i.e. RU32(mean_hat - half) <= v <= RD32(mean_hat + half)
+        ctl.bounds.lo = fmaxf(ctl.bounds.lo, __double2float_ru(u.mean_hat - u.half));
+        ctl.bounds.hi = fminf(ctl.bounds.hi, __double2float_rd(u.mean_hat + u.half));
+    }
+}
+
 // The surrogate stage of k_clip_regs, after the first evaluation: the
 // 16-point sketch and the features; in surrogate mode also the network's
 // prediction (wave 0, one hidden unit per lane), which narrows the bounds of
@@ -455,27 +481,7 @@ __device__ inline bool surrogate_stage(const ClipArgs &a, float2v (&vp)[FB][EPT 
             const float h2 = gelu(z[f]);
             const double y0 = wave_sum(double(h2 * w30)) + double(b30);
             const double y1 = wave_sum(double(h2 * w31)) + double(b31);
-            if (lane == 0) {
-                Surrogate u = sur_s[f];
-                u.mean_hat = u.m0 + y0 * u.s0;
-                u.std_hat = u.s0 * exp(y1);
-                u.half = a.cutoff * (1.0 + a.widen) * u.std_hat;
-                // no warm start in small bins or where the predicted interval reaches
-                // zero (low counts): their clip can have several fixed points (for low
-                // counts one per photon-number cluster), and a warm start could settle
-                // on another one than the plain clip
-                u.warm = u.on && u.n0 >= double(kWarmMinMembers) && u.s0 > 0.0 && ctl[f].go &&
-                         u.mean_hat - u.half > 0.0;
-                if (u.warm) {
-                    // pass 0 keeps the members within both its own bounds and
-                    // |v - mean_hat| <= half, i.e. RU32(mean_hat - half) <= v <= RD32(mean_hat + half)
-                    PassCtl c = ctl[f];
-                    c.bounds.lo = fmaxf(c.bounds.lo, __double2float_ru(u.mean_hat - u.half));
-                    c.bounds.hi = fminf(c.bounds.hi, __double2float_rd(u.mean_hat + u.half));
-                    ctl[f] = c;
-                }
-                sur_s[f] = u;
-            }
+            if (lane == 0) warm_start(a, sur_s[f], ctl[f], u_mean(sur_s[f], y0), u_std(sur_s[f], y1));
         }
     }
     __syncthreads();
@@ -490,14 +496,14 @@ __device__ __forceinline__ void clip_body(const ClipArgs &a, int g, int bin) {
     constexpr int NW = BLOCK / kWave;
     constexpr int FPW = (FB + NW - 1) / NW;  // frames finished per wave
     static_assert(FB >= 1 && BLOCK % kWave == 0, "whole waves, at least one frame");
-    constexpr bool SKETCH = MODE != MODE_CLIP;
-    constexpr bool SUR = MODE == MODE_SURROGATE;
+    constexpr bool SKETCH = MODE == MODE_FEATURES || MODE == MODE_SURROGATE;
+    constexpr bool SUR = MODE == MODE_SURROGATE || MODE == MODE_WARM;
     __shared__ uint32_t hist[SKETCH ? FB : 1][SKETCH ? NW : 1][17];
     __shared__ float sk_s[FB][16];          // sketch bounds
     __shared__ float feat_s[FB][SS_MLP_IN];
     __shared__ Surrogate sur_s[FB];
-    __shared__ uint16_t wts_s[SUR ? SS_MLP_PARAMS : 2];
-    __shared__ float h1_s[SUR ? FB : 1][SS_MLP_HID];
+    __shared__ uint16_t wts_s[MODE == MODE_SURROGATE ? SS_MLP_PARAMS : 2];
+    __shared__ float h1_s[MODE == MODE_SURROGATE ? FB : 1][SS_MLP_HID];
     __shared__ float w_s[WLDS ? EPT * BLOCK : 1];
     __shared__ float2 rem_s[NW][FB][kRemCap];
     __shared__ int cnt_s[NW][FB];
@@ -591,7 +597,7 @@ __device__ __forceinline__ void clip_body(const ClipArgs &a, int g, int bin) {
 #pragma unroll
                 for (int e = 0; e < EPT; ++e) SS_V(f, e) = buffer_load_f32(rf[f], uint32_t(ix[e]) * 4u, 0u);
         }
-        if constexpr (SUR) {
+        if constexpr (MODE == MODE_SURROGATE) {
             // the network's parameters, while the gathers are in flight
             const uint4 *src = reinterpret_cast<const uint4 *>(a.w16);
             uint4 *dst = reinterpret_cast<uint4 *>(wts_s);
@@ -719,17 +725,25 @@ __device__ __forceinline__ void clip_body(const ClipArgs &a, int g, int bin) {
         plan(a, st, c, 0, false);
         if (f >= nf) c.go = 0;
         ctl[f] = c;
-        if constexpr (SKETCH) {
+        if constexpr (SKETCH || SUR) {
             const Stats s0 = stats_from(st, Kf);
             Surrogate u{};
             u.n0 = st[S_N];
             u.m0 = s0.mean;
             u.s0 = s0.std;
             u.on = f < nf && st[S_N] >= 0.5;
+            if constexpr (MODE == MODE_WARM) {
+                // the given prediction of this (frame, bin)
+                const int64_t o = int64_t(f0 + f) * a.n_bins + bin;
+                if (u.on) warm_start(a, u, c, a.pred_mean[o], a.pred_std[o]);
+                ctl[f] = c;
+            }
             sur_s[f] = u;
             // v <= m0 + t s0 exactly when v <= RD32(m0 + t s0)
+            if constexpr (SKETCH) {
 #pragma unroll
-            for (int k = 0; k < 16; ++k) sk_s[f][k] = __double2float_rd(s0.mean + (-3.75 + 0.5 * k) * s0.std);
+                for (int k = 0; k < 16; ++k) sk_s[f][k] = __double2float_rd(s0.mean + (-3.75 + 0.5 * k) * s0.std);
+            }
         }
     }
     __syncthreads();
@@ -1088,6 +1102,7 @@ void launch_shape(const ClipArgs &a, int mode, hipStream_t stream) {
     switch (mode) {
         case MODE_FEATURES: launch_regs<BLOCK, EPT, FB, WPE, MODE_FEATURES, WLDS>(a, stream); break;
         case MODE_SURROGATE: launch_regs<BLOCK, EPT, FB, WPE, MODE_SURROGATE, WLDS>(a, stream); break;
+        case MODE_WARM: launch_regs<BLOCK, EPT, FB, WPE, MODE_WARM, WLDS>(a, stream); break;
         default: launch_regs<BLOCK, EPT, FB, WPE, MODE_CLIP, WLDS>(a, stream); break;
     }
 }
@@ -1298,6 +1313,8 @@ struct SurrogateIo {
     const uint16_t *w16 = nullptr;
     float widen = 0.0f;
     int32_t *accepted = nullptr;
+    const double *pred_mean = nullptr;
+    const double *pred_std = nullptr;
 };
 
 // Checks one call's arguments and fills the kernel arguments; returns an
@@ -1324,6 +1341,10 @@ int clip_args(const float *frames, const float *norm, const uint8_t *mask, int32
         if (io.mode == ss::MODE_SURROGATE &&
             (p->error_model != SS_AZIMUTHAL || !(p->cutoff > 0.0f) || !io.w16 ||
              (reinterpret_cast<uintptr_t>(io.w16) & 15u) != 0 || !(io.widen >= 0.0f) || !io.accepted))
+            return SS_EINVAL;
+        if (io.mode == ss::MODE_WARM &&
+            (p->error_model != SS_AZIMUTHAL || !(p->cutoff > 0.0f) || !io.pred_mean || !io.pred_std ||
+             !(io.widen >= 0.0f) || !io.accepted))
             return SS_EINVAL;
     }
     if (n_frames == 0) return SS_OK;
@@ -1368,6 +1389,8 @@ int clip_args(const float *frames, const float *norm, const uint8_t *mask, int32
     a.w16 = io.w16;
     a.widen = double(io.widen);
     a.accepted = io.accepted;
+    a.pred_mean = io.pred_mean;
+    a.pred_std = io.pred_std;
     if (csr->bin_order) {
         int64_t sum = 0;
         for (int c = 0; c < SS_N_CLASSES; ++c) {
@@ -1390,7 +1413,7 @@ int clip_entry(const float *frames, const float *norm, const uint8_t *mask, int3
     const int rc = clip_args(frames, norm, mask, n_frames, csr, p, out, integrate_only, io, a, empty);
     if (rc != SS_OK || empty) return rc;
     ss::dispatch(a, csr, n_frames, io.mode, stream);
-    if (io.mode == ss::MODE_SURROGATE) {
+    if (io.mode == ss::MODE_SURROGATE || io.mode == ss::MODE_WARM) {
         // the groups holding a refused bin, clipped again from scratch
         a.redo = io.accepted;
         ss::dispatch(a, csr, n_frames, ss::MODE_CLIP, stream);
@@ -1433,6 +1456,19 @@ extern "C" int ss_sigma_clip_surrogate(const float *frames, const float *norm, c
     SurrogateIo io;
     io.mode = ss::MODE_SURROGATE;
     io.w16 = w16;
+    io.widen = widen;
+    io.accepted = accepted;
+    return clip_entry(frames, norm, mask, n_frames, csr, params, out, false, io, stream);
+}
+
+extern "C" int ss_sigma_clip_warm(const float *frames, const float *norm, const uint8_t *mask, int32_t n_frames,
+                                  const ss_csr *csr, const ss_params *params, const double *pred_mean,
+                                  const double *pred_std, float widen, const ss_profile *out, int32_t *accepted,
+                                  hipStream_t stream) {
+    SurrogateIo io;
+    io.mode = ss::MODE_WARM;
+    io.pred_mean = pred_mean;
+    io.pred_std = pred_std;
     io.widen = widen;
     io.accepted = accepted;
     return clip_entry(frames, norm, mask, n_frames, csr, params, out, false, io, stream);

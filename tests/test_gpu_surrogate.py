@@ -204,3 +204,44 @@ def test_trained_surrogate_matches_oracle_and_saves_passes(dev, small):
     # the trained network's warm start is accepted in most bins and saves passes
     assert n_acc >= 0.5 * 2 * geo.n_bins
     assert passes_sur < passes_plain
+
+
+def test_warm_start_from_given_predictions_matches_oracle(dev, small):
+    """ss_sigma_clip_warm with two predictors, the plain clip's own converged
+    profile (a perfect predictor) and the previous frame's profile: the
+    states, statistics and passes of the oracle's warm clip with the same
+    predictions; with the perfect predictor the accepted bins take fewer
+    passes than the plain clip."""
+    g, sc, geo, frames = small
+    _say("case: warm start from given predictions, small config x3")
+    params = api.Params(cutoff=3.0, max_iter=32)
+    x = torch.from_numpy(frames[:3]).to(dev)
+    plain = api.sigma_clip(x, geo, params)
+    prev = {k: torch.roll(plain[k], 1, dims=0).contiguous() for k in ("mean", "std")}
+    for name, (pm, ps) in (("own", (plain["mean"], plain["std"])), ("previous", (prev["mean"], prev["std"]))):
+        got, state = api.sigma_clip_warm(x, geo, params, pm, ps, widen=0.1)
+        torch.cuda.synchronize()
+        state = state.cpu().numpy()
+        pmh, psh = pm.cpu().numpy(), ps.cpu().numpy()
+        n_acc = passes_warm = passes_plain = 0
+        for f in range(3):
+            ref = Q.warm_clip(frames[f], None, sc.csr, pmh[f], psh[f], sc.mask, 3.0, 32, 0.1)
+            gp = {k: v[f].cpu().numpy() for k, v in got.items()}
+            pl = {k: v[f].cpu().numpy() for k, v in plain.items()}
+            assert np.array_equal(state[f], ref["state"]), (name, f, np.nonzero(state[f] != ref["state"])[0][:5])
+            for r in range(sc.csr.n_bins):
+                if state[f, r] == 1:
+                    n_acc += 1
+                    passes_warm += gp["n_iter"][r] + gp["converged"][r]
+                    passes_plain += pl["n_iter"][r] + pl["converged"][r]
+                    for k in ("mean", "std", "sem", "sum_w"):
+                        tol = 1e-5 * abs(ref[k][r]) + 1e-7 * abs(ref["mean"][r])
+                        assert abs(gp[k][r] - ref[k][r]) <= tol, (name, f, r, k)
+                    assert gp["n_members"][r] == ref["n_members"][r] and gp["n_iter"][r] == ref["n_iter"][r]
+                else:
+                    for k in ("mean", "std", "sem", "sum_w", "n_members", "n_iter", "converged"):
+                        assert gp[k][r] == pl[k][r], (name, f, r, k)
+        _say(f"  {name}: accepted {n_acc} of {3 * geo.n_bins} bins, {passes_warm} passes instead of {passes_plain}")
+        assert n_acc >= 0.5 * 3 * geo.n_bins
+        if name == "own":
+            assert passes_warm < passes_plain
