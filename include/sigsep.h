@@ -238,6 +238,22 @@ int ss_correct(const uint16_t *raw, int32_t n_frames, int64_t n_pix,
                float *out, int64_t *n_invalid, hipStream_t stream);
 
 /*
+ * ss_correct_indexed -- ss_correct of frames picked from a ring of raw
+ * frames by a device-side index (serving support: frames that arrive into a
+ * device ring are corrected where they lie, with no copy).  Output frame f
+ * is the correction of ring frame frame_index[f]; an index outside
+ * [0, ring_frames) gives a frame of invalid words (all NaN, all counted).
+ *   ring        [dev] uint16 [ring_frames][n_pix]
+ *   frame_index [dev] int64 [n_frames]
+ *   other arguments as ss_correct.
+ * Errors: those of ss_correct; SS_ESIZE for ring_frames < 0, SS_EINVAL for a
+ * null frame_index with n_frames > 0.
+ */
+int ss_correct_indexed(const uint16_t *ring, int64_t ring_frames, const int64_t *frame_index,
+                       int32_t n_frames, int64_t n_pix, const float *pedestal, const float *gain,
+                       const float *norm, float *out, int64_t *n_invalid, hipStream_t stream);
+
+/*
  * ss_integrate_csr -- azimuthal average with uncertainties (Sec. 2.2, eqs. avg
  * to sem2), no clipping: ss_sigma_clip with max_iter forced to 0.
  */

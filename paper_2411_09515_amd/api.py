@@ -215,6 +215,32 @@ def correct(raw, pedestal, gain, norm=None, out=None, n_invalid=None):
     return out, n_invalid
 
 
+def correct_indexed(ring, frame_index, pedestal, gain, norm=None, out=None, n_invalid=None):
+    """Correction of ring frames picked by a device index: ring [K, N] of
+    16-bit words, frame_index [F] int64 on the device -> out [F, N] float32
+    (an index outside the ring gives an all-invalid frame)."""
+    if not isinstance(ring, torch.Tensor) or ring.dim() != 2:
+        raise ValueError("ring: expected a [K, N] tensor of 16-bit words")
+    K, N = ring.shape
+    _arg(ring, "ring", (torch.uint16, torch.int16), (K, N))
+    _arg(frame_index, "frame_index", torch.int64, (None,))
+    F = frame_index.shape[0]
+    _arg(pedestal, "pedestal", torch.float32, (3, N))
+    _arg(gain, "gain", torch.float32, (3, N))
+    if pedestal is None or gain is None:
+        raise ValueError("pedestal and gain are required")
+    _arg(norm, "norm", torch.float32, (N,))
+    if out is None:
+        out = torch.empty((F, N), dtype=torch.float32, device=ring.device)
+    if n_invalid is None:
+        n_invalid = torch.empty(F, dtype=torch.int64, device=ring.device)
+    _arg(out, "out", torch.float32, (F, N))
+    _arg(n_invalid, "n_invalid", torch.int64, (F,))
+    B.check("ss_correct_indexed", B.lib().ss_correct_indexed(_p(ring), K, _p(frame_index), F, N, _p(pedestal),
+                                                             _p(gain), _p(norm), _p(out), _p(n_invalid), _stream()))
+    return out, n_invalid
+
+
 # -- statistics -------------------------------------------------------------------------
 
 def new_profile(n_frames, n_bins, device="cuda"):

@@ -35,7 +35,7 @@ SS_CLASSIFY_SCRATCH_BYTES = 64 << 20
 
 EXPORTED = (
     "ss_strerror", "ss_version", "ss_build_csr", "ss_csr_schedule", "ss_class_rows", "ss_radial_coords",
-    "ss_correct",
+    "ss_correct", "ss_correct_indexed",
     "ss_integrate_csr", "ss_sigma_clip", "ss_classify_workspace", "ss_classify", "ss_classify_noalloc",
     "ss_compress", "ss_peakfind",
     "ss_clip_features", "ss_surrogate_targets", "ss_mlp_forward", "ss_mlp_grad_workspace", "ss_mlp_grad",
@@ -117,6 +117,8 @@ def lib():
         L.ss_radial_coords.argtypes = [i32, i32, f64, f64, f64, f64, i32, f64, vp, vp, P(f64), P(f64)]
         L.ss_correct.restype = ctypes.c_int
         L.ss_correct.argtypes = [vp, i32, i64, vp, vp, vp, vp, vp, vp]
+        L.ss_correct_indexed.restype = ctypes.c_int
+        L.ss_correct_indexed.argtypes = [vp, i64, vp, i32, i64, vp, vp, vp, vp, vp, vp]
         for name in ("ss_integrate_csr", "ss_sigma_clip"):
             fn = getattr(L, name)
             fn.restype = ctypes.c_int

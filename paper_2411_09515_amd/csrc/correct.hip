@@ -87,6 +87,24 @@ __device__ inline float correct_one(uint32_t word, const PixelCal c, bool has_no
     return bad ? __builtin_nanf("") : v;
 }
 
+// Raw words of frame f: frame f of the batch, or, with a frame index, frame
+// frame_index[f] of a ring of ring_frames frames.  An index outside the ring
+// reads as invalid words (gain code 10: NaN, counted) instead of memory.
+struct RawFrames {
+    const uint16_t *raw;
+    const int64_t *frame_index;  // [n_frames] or null
+    int64_t ring_frames;
+};
+
+__device__ inline const uint16_t *frame_words(const RawFrames &r, int f, int64_t n_pix, bool &ok) {
+    int64_t fi = f;
+    if (r.frame_index) fi = r.frame_index[f];
+    ok = uint64_t(fi) < uint64_t(r.ring_frames);
+    return r.raw + (ok ? fi : 0) * n_pix;
+}
+
+constexpr uint32_t kInvalidPair = 0x80008000u;  // two words with gain code 10
+
 #ifndef SS_CORRECT_UNROLL
 #define SS_CORRECT_UNROLL 4
 #endif
@@ -94,7 +112,7 @@ constexpr int kFrameUnroll = SS_CORRECT_UNROLL;
 
 // Vector path: n_pix % 4 == 0 and 8/16-byte aligned buffers.
 __global__ __launch_bounds__(kCorrectBlock) void k_correct_vec(
-    const uint16_t *__restrict__ raw, int n_frames, int64_t n_pix, const float *__restrict__ ped,
+    const RawFrames raw, int n_frames, int64_t n_pix, const float *__restrict__ ped,
     const float *__restrict__ gain, const float *__restrict__ norm, float *__restrict__ out,
     int64_t *__restrict__ n_invalid) {
     const int64_t p0 = (int64_t(blockIdx.x) * kCorrectBlock + threadIdx.x) * kVec;
@@ -107,7 +125,9 @@ __global__ __launch_bounds__(kCorrectBlock) void k_correct_vec(
 #pragma unroll
         for (int u = 0; u < kFrameUnroll; ++u) {
             const int f = min(f0 + u, n_frames - 1);
-            w[u] = *reinterpret_cast<const uint2 *>(raw + int64_t(f) * n_pix + p0);
+            bool ok;
+            const uint16_t *fr = frame_words(raw, f, n_pix, ok);
+            w[u] = ok ? *reinterpret_cast<const uint2 *>(fr + p0) : make_uint2(kInvalidPair, kInvalidPair);
         }
 #pragma unroll
         for (int u = 0; u < kFrameUnroll; ++u) {
@@ -132,7 +152,7 @@ __global__ __launch_bounds__(kCorrectBlock) void k_correct_vec(
 constexpr int kFewFrames = 2;
 
 __global__ __launch_bounds__(kCorrectBlock) void k_correct_few(
-    const uint16_t *__restrict__ raw, int n_frames, int64_t n_pix, const float *__restrict__ ped,
+    const RawFrames raw, int n_frames, int64_t n_pix, const float *__restrict__ ped,
     const float *__restrict__ gain, const float *__restrict__ norm, float *__restrict__ out,
     int64_t *__restrict__ n_invalid) {
     const int64_t p0 = (int64_t(blockIdx.x) * kCorrectBlock + threadIdx.x) * kVec;
@@ -145,7 +165,9 @@ __global__ __launch_bounds__(kCorrectBlock) void k_correct_few(
         rn[k] = 1.0 / double(nm[k]);
     }
     for (int f = 0; f < n_frames; ++f) {
-        const uint2 w = *reinterpret_cast<const uint2 *>(raw + int64_t(f) * n_pix + p0);
+        bool ok;
+        const uint16_t *fr = frame_words(raw, f, n_pix, ok);
+        const uint2 w = ok ? *reinterpret_cast<const uint2 *>(fr + p0) : make_uint2(kInvalidPair, kInvalidPair);
         const uint32_t words[kVec] = {w.x & 0xFFFFu, w.x >> 16, w.y & 0xFFFFu, w.y >> 16};
         int invalid = 0;
         float o[kVec];
@@ -167,7 +189,7 @@ __global__ __launch_bounds__(kCorrectBlock) void k_correct_few(
 
 // Scalar path for any size and alignment: one thread per pixel, all frames.
 __global__ __launch_bounds__(kCorrectBlock) void k_correct_scalar(
-    const uint16_t *__restrict__ raw, int n_frames, int64_t n_pix, const float *__restrict__ ped,
+    const RawFrames raw, int n_frames, int64_t n_pix, const float *__restrict__ ped,
     const float *__restrict__ gain, const float *__restrict__ norm, float *__restrict__ out,
     int64_t *__restrict__ n_invalid) {
     const int64_t i = int64_t(blockIdx.x) * kCorrectBlock + threadIdx.x;
@@ -176,7 +198,9 @@ __global__ __launch_bounds__(kCorrectBlock) void k_correct_scalar(
     for (int f = 0; f < n_frames; ++f) {
         const int64_t at = int64_t(f) * n_pix + i;
         int invalid = 0;
-        out[at] = correct_one(raw[at], cal, norm != nullptr, invalid);
+        bool ok;
+        const uint16_t *fr = frame_words(raw, f, n_pix, ok);
+        out[at] = correct_one(ok ? fr[i] : 0x8000u, cal, norm != nullptr, invalid);
         if (invalid && n_invalid) atomicAdd(reinterpret_cast<unsigned long long *>(n_invalid + f),
                                             (unsigned long long)invalid);
     }
@@ -187,33 +211,52 @@ bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) ==
 }  // namespace
 }  // namespace ss
 
-extern "C" int ss_correct(const uint16_t *raw, int32_t n_frames, int64_t n_pix, const float *pedestal,
-                          const float *gain, const float *norm, float *out, int64_t *n_invalid,
-                          hipStream_t stream) {
+namespace {
+
+int correct_entry(const ss::RawFrames &rf, int32_t n_frames, int64_t n_pix, const float *pedestal, const float *gain,
+                  const float *norm, float *out, int64_t *n_invalid, hipStream_t stream) {
     using namespace ss;
     if (n_frames < 0 || n_pix < 0 || n_pix >= (int64_t(1) << 31)) return SS_ESIZE;
     if (n_frames == 0) return SS_OK;
-    if (!raw || !pedestal || !gain || !out) return SS_EINVAL;
+    if (!rf.raw || !pedestal || !gain || !out) return SS_EINVAL;
     if (n_invalid) {
         k_fill_i64<<<1, 64, 0, stream>>>(n_invalid, n_frames, 0);
         SS_RETURN_IF_LAUNCH_FAILED();
     }
     if (n_pix == 0) return SS_OK;
-    const bool vec = (n_pix % kVec == 0) && aligned16(raw) && aligned16(out);
+    const bool vec = (n_pix % kVec == 0) && aligned16(rf.raw) && aligned16(out);
     if (vec) {
         const int64_t threads = n_pix / kVec;
         const int64_t blocks = (threads + kCorrectBlock - 1) / kCorrectBlock;
         if (n_frames <= kFewFrames)
             k_correct_few<<<dim3(uint32_t(blocks)), kCorrectBlock, 0, stream>>>(
-                raw, n_frames, n_pix, pedestal, gain, norm, out, n_invalid);
+                rf, n_frames, n_pix, pedestal, gain, norm, out, n_invalid);
         else
             k_correct_vec<<<dim3(uint32_t(blocks)), kCorrectBlock, 0, stream>>>(
-                raw, n_frames, n_pix, pedestal, gain, norm, out, n_invalid);
+                rf, n_frames, n_pix, pedestal, gain, norm, out, n_invalid);
     } else {
         const int64_t blocks = (n_pix + kCorrectBlock - 1) / kCorrectBlock;
         k_correct_scalar<<<dim3(uint32_t(blocks)), kCorrectBlock, 0, stream>>>(
-            raw, n_frames, n_pix, pedestal, gain, norm, out, n_invalid);
+            rf, n_frames, n_pix, pedestal, gain, norm, out, n_invalid);
     }
     SS_RETURN_IF_LAUNCH_FAILED();
     return SS_OK;
+}
+
+}  // namespace
+
+extern "C" int ss_correct(const uint16_t *raw, int32_t n_frames, int64_t n_pix, const float *pedestal,
+                          const float *gain, const float *norm, float *out, int64_t *n_invalid,
+                          hipStream_t stream) {
+    return correct_entry(ss::RawFrames{raw, nullptr, int64_t(n_frames)}, n_frames, n_pix, pedestal, gain, norm, out,
+                         n_invalid, stream);
+}
+
+extern "C" int ss_correct_indexed(const uint16_t *ring, int64_t ring_frames, const int64_t *frame_index,
+                                  int32_t n_frames, int64_t n_pix, const float *pedestal, const float *gain,
+                                  const float *norm, float *out, int64_t *n_invalid, hipStream_t stream) {
+    if (ring_frames < 0) return SS_ESIZE;
+    if (n_frames > 0 && !frame_index) return SS_EINVAL;
+    return correct_entry(ss::RawFrames{ring, frame_index, ring_frames}, n_frames, n_pix, pedestal, gain, norm, out,
+                         n_invalid, stream);
 }

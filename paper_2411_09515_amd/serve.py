@@ -79,18 +79,17 @@ class Detector:
     def slot_bytes(self):
         N, nb, B_ = self.geom.n_pix, self.geom.n_bins, self.max_batch
         ws = api.workspace_bytes(B_, N, nb)
-        # raw + frames, profile, results and their packed copies, counts
-        per = (N * (2 + 4) + nb * (4 * 8 + 3 * 4) + 2 * (self.kept_capacity * 8 + self.peak_capacity * B.PEAK_BYTES)
+        # frames, profile, results and their packed copies, counts
+        per = (N * 4 + nb * (4 * 8 + 3 * 4) + 2 * (self.kept_capacity * 8 + self.peak_capacity * B.PEAK_BYTES)
                + 32)
         return B_ * per + ws
 
 
 class _Slot:
-    def __init__(self, det: Detector, device, stream, full_profile=False):
+    def __init__(self, det: Detector, device, stream, full_profile=False, n_arenas=1):
         F, N, nb = det.max_batch, det.geom.n_pix, det.geom.n_bins
         self.det = det
         self.full_profile = full_profile
-        self.raw = torch.empty((F, N), dtype=torch.int16, device=device)
         self.frames = torch.empty((F, N), dtype=torch.float32, device=device)
         self.n_invalid = torch.empty(F, dtype=torch.int64, device=device)
         self.profile = api.new_profile(F, nb, device)
@@ -111,19 +110,23 @@ class _Slot:
         self.d_idx = torch.empty(F, dtype=torch.int64, device=device)
         self.h_counts = torch.empty((2, F), dtype=torch.int64, pin_memory=True)
         self.h_offsets = torch.empty(2 * (F + 1), dtype=torch.int64, pin_memory=True)
-        self.h_mean = torch.empty((F, nb), dtype=torch.float64, pin_memory=True)
-        self.h_std = torch.empty((F, nb), dtype=torch.float64, pin_memory=True)
-        self.h_index = torch.empty(F * det.kept_capacity, dtype=torch.int32, pin_memory=True)
-        self.h_value = torch.empty(F * det.kept_capacity, dtype=torch.float32, pin_memory=True)
-        self.h_peaks = torch.empty((F * det.peak_capacity, B.PEAK_BYTES), dtype=torch.uint8, pin_memory=True)
-        self.h_rest = {}
-        if full_profile:
-            self.h_rest = {k: torch.empty((F, nb), dtype=self.profile[k].dtype, pin_memory=True)
-                           for k in ("sem", "sum_w", "n_members", "n_iter", "converged")}
+        # results land in one of n_arenas pinned host arenas, in turn per batch
+        rest = ("sem", "sum_w", "n_members", "n_iter", "converged") if full_profile else ()
+        self.arenas = []
+        for _ in range(n_arenas):
+            a = dict(mean=torch.empty((F, nb), dtype=torch.float64, pin_memory=True),
+                     std=torch.empty((F, nb), dtype=torch.float64, pin_memory=True),
+                     index=torch.empty(F * det.kept_capacity, dtype=torch.int32, pin_memory=True),
+                     value=torch.empty(F * det.kept_capacity, dtype=torch.float32, pin_memory=True),
+                     peaks=torch.empty((F * det.peak_capacity, B.PEAK_BYTES), dtype=torch.uint8, pin_memory=True))
+            for k in rest:
+                a[k] = torch.empty((F, nb), dtype=self.profile[k].dtype, pin_memory=True)
+            self.arenas.append(a)
+        self.rest = rest
+        self.arena = 0
         # touch every page of the pinned buffers now: first touches fault, and
         # would otherwise land inside the serving loop
-        for t in (self.h_idx, self.h_counts, self.h_offsets, self.h_mean, self.h_std, self.h_index, self.h_value,
-                  self.h_peaks, *self.h_rest.values()):
+        for t in (self.h_idx, self.h_counts, self.h_offsets, *(t for a in self.arenas for t in a.values())):
             t.zero_()
         self.stream = stream
         self.graphs = {}     # batch size -> captured device work of one batch
@@ -134,11 +137,12 @@ class _Slot:
 
     def device_work(self, F):
         """The whole path on the first F ring frames named by d_idx, on the
-        current stream: gather, correct, clip, classify, pack."""
+        current stream: correct (reading the ring frames where they lie),
+        clip, classify, pack."""
         d = self.det
-        torch.index_select(d.ring, 0, self.d_idx[:F], out=self.raw[:F])
         frames = self.frames[:F]
-        api.correct(self.raw[:F], d.pedestal, d.gain, d.geom.norm, out=frames, n_invalid=self.n_invalid[:F])
+        api.correct_indexed(d.ring, self.d_idx[:F], d.pedestal, d.gain, d.geom.norm, out=frames,
+                            n_invalid=self.n_invalid[:F])
         prof = {k: v[:F] for k, v in self.profile.items()}
         api.sigma_clip(frames, d.geom, d.params, out=prof)
         out = {k: v[:F] for k, v in self.out.items()}
@@ -169,12 +173,18 @@ def _keep_result_buffers_on_the_heap():
 class Server:
     """Continuous batching over detectors within an HBM budget (bytes).
 
-    With ``tune_malloc`` (default) the process's malloc thresholds are set
-    so that per-request result arrays come from the heap (see
+    With ``copy_results`` (default) every request's result arrays are its
+    own copies.  Without it they are views into the slot's pinned result
+    arenas (two per slot, used in turn), valid until that slot has finished
+    its next batch: a consumer that stores or forwards each result as it
+    completes avoids one host copy of every kept pixel.  With
+    ``tune_malloc`` (default) the process's malloc thresholds are set so
+    that per-request result copies come from the heap (see
     ``_keep_result_buffers_on_the_heap``)."""
 
     def __init__(self, detectors, hbm_budget=8 << 30, device="cuda", max_slots_per_detector=2, tune_malloc=True,
-                 full_profile=False):
+                 full_profile=False, copy_results=True):
+        self.copy_results = copy_results
         if tune_malloc:
             _keep_result_buffers_on_the_heap()
         self.detectors = list(detectors)
@@ -198,7 +208,8 @@ class Server:
             for i, d in enumerate(self.detectors):
                 b = d.slot_bytes()
                 if per_det[i] < max_slots_per_detector and used + b <= hbm_budget:
-                    self.slots.append(_Slot(d, self.device, self.streams[i], full_profile))
+                    self.slots.append(_Slot(d, self.device, self.streams[i], full_profile,
+                                            1 if copy_results else 2))
                     per_det[i] += 1
                     used += b
                     progress = True
@@ -223,10 +234,9 @@ class Server:
             slot.h_offsets[:2 * (F + 1)].copy_(slot.packed["offsets"][:2 * (F + 1)], non_blocking=True)
             slot.h_counts[0, :F].copy_(slot.out["n_kept"][:F], non_blocking=True)
             slot.h_counts[1, :F].copy_(slot.out["n_peaks"][:F], non_blocking=True)
-            slot.h_mean[:F].copy_(slot.profile["mean"][:F], non_blocking=True)
-            slot.h_std[:F].copy_(slot.profile["std"][:F], non_blocking=True)
-            for k, h in slot.h_rest.items():
-                h[:F].copy_(slot.profile[k][:F], non_blocking=True)
+            A = slot.arenas[slot.arena]
+            for k in ("mean", "std", *slot.rest):
+                A[k][:F].copy_(slot.profile[k][:F], non_blocking=True)
             slot.ev_counts.record(slot.stream)
         slot.batch = batch
         slot.phase = 1
@@ -237,33 +247,39 @@ class Server:
         tp = int(slot.h_offsets[2 * F + 1])
         with torch.cuda.stream(slot.stream):
             # exactly the packed results: one contiguous copy per kind
+            A = slot.arenas[slot.arena]
             if tk:
-                slot.h_index[:tk].copy_(slot.packed["index"][:tk], non_blocking=True)
-                slot.h_value[:tk].copy_(slot.packed["value"][:tk], non_blocking=True)
+                A["index"][:tk].copy_(slot.packed["index"][:tk], non_blocking=True)
+                A["value"][:tk].copy_(slot.packed["value"][:tk], non_blocking=True)
             if tp:
-                slot.h_peaks[:tp].copy_(slot.packed["peaks"][:tp], non_blocking=True)
+                A["peaks"][:tp].copy_(slot.packed["peaks"][:tp], non_blocking=True)
             slot.ev_done.record(slot.stream)
         slot.phase = 2
 
     def _finish(self, slot: _Slot, now):
         F = len(slot.batch)
+        A = slot.arenas[slot.arena]
         counts = slot.h_counts[:, :F].numpy()
         off = slot.h_offsets[:2 * (F + 1)].numpy()
         for f, r in enumerate(slot.batch):
             k0, k1 = int(off[f]), int(off[f + 1])
             p0, p1 = int(off[F + 1 + f]), int(off[F + 2 + f])
             r.n_kept, r.n_peaks = int(counts[0, f]), int(counts[1, f])
-            r.kept_index = slot.h_index[k0:k1].numpy().view(np.uint32).copy()
-            r.kept_value = slot.h_value[k0:k1].numpy().copy()
-            r.peaks = api.peaks_to_numpy(slot.h_peaks[p0:p1], p1 - p0)
-            r.mean = slot.h_mean[f].numpy().copy()
-            r.std = slot.h_std[f].numpy().copy()
-            for k, h in slot.h_rest.items():
-                setattr(r, k, h[f].numpy().copy())
+            r.kept_index = A["index"][k0:k1].numpy().view(np.uint32)
+            r.kept_value = A["value"][k0:k1].numpy()
+            r.peaks = A["peaks"][p0:p1].numpy().reshape(-1).view(api.PEAK_DTYPE)
+            r.mean = A["mean"][f].numpy()
+            r.std = A["std"][f].numpy()
+            for k in slot.rest:
+                setattr(r, k, A[k][f].numpy())
+            if self.copy_results:
+                for k in ("kept_index", "kept_value", "peaks", "mean", "std", *slot.rest):
+                    setattr(r, k, getattr(r, k).copy())
             r.batch_size = F
             r.t_done = now
         slot.batch = []
         slot.phase = 0
+        slot.arena = (slot.arena + 1) % len(slot.arenas)
 
     def capture_graphs(self):
         """Capture every slot's device work for every batch size as a HIP

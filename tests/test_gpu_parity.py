@@ -401,3 +401,25 @@ def test_dense_candidates(dev, snr, patch):
         gp = api.peaks_to_numpy(out["peaks"][f], int(out["n_peaks"][f]))
         assert np.array_equal(gp["index"].astype(np.int64), rp["index"]), (f, gp.size, rp.size)
         assert rp.size > 10, rp.size
+
+
+def test_correct_indexed_matches_correct(dev, jungfrau):
+    """ss_correct_indexed: frames picked from a ring by a device index are
+    corrected bit for bit as ss_correct corrects the same frames; an index
+    outside the ring gives an all-NaN frame, every pixel counted invalid."""
+    g, sc, geo, raw, ped, gain = jungfrau
+    _say("case: correct_indexed, ring of 3 jungfrau-4m frames")
+    ring = torch.from_numpy(raw.view(np.int16)).to(dev)
+    ped_d, gain_d = torch.from_numpy(ped).to(dev), torch.from_numpy(gain).to(dev)
+    for idx in ([2, 0], [1], [0, 2, 1, 1]):
+        fi = torch.tensor(idx, dtype=torch.int64, device=dev)
+        got, nb = api.correct_indexed(ring, fi, ped_d, gain_d, geo.norm)
+        want, nw = api.correct(torch.from_numpy(raw[idx]).to(dev), ped_d, gain_d, geo.norm)
+        torch.cuda.synchronize()
+        assert torch.equal(nb, nw)
+        assert np.array_equal(got.cpu().numpy().view(np.uint32), want.cpu().numpy().view(np.uint32)), idx
+    fi = torch.tensor([1, 3, -1], dtype=torch.int64, device=dev)
+    got, nb = api.correct_indexed(ring, fi, ped_d, gain_d, geo.norm)
+    torch.cuda.synchronize()
+    assert nb.cpu().tolist()[1:] == [g.n_pix, g.n_pix]
+    assert torch.isnan(got[1:]).all() and not torch.isnan(got[0]).all()
