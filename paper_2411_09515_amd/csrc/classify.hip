@@ -59,6 +59,8 @@ struct alignas(16) SegF {
 
 struct Workspace {
     SegF *tablef;       // [n_frames][n_bins + 1]
+    SegF *tablet;       // [n_frames][n_bins + 1] threshold lines (noise 0), or null
+    float *tolf;        // [n_frames] tolerance of the threshold lines, or null
     uint32_t *counts;   // per tile: kept | peaks << 16, [n_frames][tiles]
     uint64_t *offsets;  // per tile: kept offset | peak offset << 32, [n_frames][tiles]
     Seg *table;         // [n_frames][n_bins + 1]
@@ -75,8 +77,10 @@ size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
 
 size_t workspace_bytes(int32_t n_frames, int64_t n_pix, int32_t n_bins) {
     const size_t tiles = size_t(n_frames) * tiles_of(n_pix);
-    return 256 + align256(size_t(n_frames) * size_t(n_bins + 1) * sizeof(SegF)) + align256(tiles * sizeof(uint32_t)) + align256(tiles * sizeof(uint64_t)) +
-           align256(size_t(n_frames) * size_t(n_bins + 1) * sizeof(Seg)) + align256(size_t(n_frames) * size_t(n_pix));
+    return 256 + 2 * align256(size_t(n_frames) * size_t(n_bins + 1) * sizeof(SegF)) +
+           align256(size_t(n_frames) * sizeof(float)) + align256(tiles * sizeof(uint32_t)) +
+           align256(tiles * sizeof(uint64_t)) + align256(size_t(n_frames) * size_t(n_bins + 1) * sizeof(Seg)) +
+           align256(size_t(n_frames) * size_t(n_pix));
 }
 
 Workspace carve(void *base, int32_t n_frames, int64_t n_pix, int32_t n_bins) {
@@ -85,6 +89,10 @@ Workspace carve(void *base, int32_t n_frames, int64_t n_pix, int32_t n_bins) {
     Workspace w;
     w.tablef = reinterpret_cast<SegF *>(p);
     p += align256(size_t(n_frames) * size_t(n_bins + 1) * sizeof(SegF));
+    w.tablet = reinterpret_cast<SegF *>(p);
+    p += align256(size_t(n_frames) * size_t(n_bins + 1) * sizeof(SegF));
+    w.tolf = reinterpret_cast<float *>(p);
+    p += align256(size_t(n_frames) * sizeof(float));
     w.counts = reinterpret_cast<uint32_t *>(p);
     p += align256(tiles * sizeof(uint32_t));
     w.offsets = reinterpret_cast<uint64_t *>(p);
@@ -99,7 +107,7 @@ Workspace carve(void *base, int32_t n_frames, int64_t n_pix, int32_t n_bins) {
 
 __global__ __launch_bounds__(kTableBlock) void k_profile_table(
     const double *__restrict__ mean, const double *__restrict__ stdv, const int32_t *__restrict__ members,
-    int32_t n_bins, Workspace ws, int32_t tiles, int64_t *n_kept, int64_t *n_peaks) {
+    int32_t n_bins, Workspace ws, int32_t tiles, int64_t *n_kept, int64_t *n_peaks, double n_pick, double snr) {
     __shared__ int32_t lo_s[SS_MAX_BINS + 1];
     __shared__ int32_t hi_s[SS_MAX_BINS + 1];
     __shared__ int32_t chunk_lo[kTableBlock];
@@ -151,6 +159,7 @@ __global__ __launch_bounds__(kTableBlock) void k_profile_table(
 
     // interval t (stored at t + 1) lies between centres t and t + 1
     Seg *tab = ws.table + int64_t(f) * (n_bins + 1);
+    double scale = 0.0;
     for (int t1 = tid; t1 <= n_bins; t1 += kTableBlock) {
         const int t = t1 - 1;
         const int lo = t >= 0 ? lo_s[t] : -1;
@@ -171,9 +180,33 @@ __global__ __launch_bounds__(kTableBlock) void k_profile_table(
         tab[t1] = s;
         // u = (t1 - 1 - lo + frac) inv_span, so mu = m_lo + dm u is a line in frac
         const double u0 = double(t1 - 1 - s.lo) * s.inv_span;
-        ws.tablef[int64_t(f) * (n_bins + 1) + t1] =
-            SegF{float(s.m_lo + s.dm * u0), float(s.dm * s.inv_span), float(s.s_lo + s.ds * u0),
-                 float(s.ds * s.inv_span)};
+        const double ma = s.m_lo + s.dm * u0, mb = s.dm * s.inv_span;
+        const double sa = s.s_lo + s.ds * u0, sb = s.ds * s.inv_span;
+        ws.tablef[int64_t(f) * (n_bins + 1) + t1] = SegF{float(ma), float(mb), float(sa), float(sb)};
+        if (ws.tablet) {
+            // Without a noise level sigma_eff = sigma, which the interpolation
+            // keeps non-negative, so both thresholds mu + n sigma are lines in
+            // frac too: keep = v > ka + kb frac, candidate = v >= ca + cb frac
+            const double ka = ma + n_pick * sa, kb = mb + n_pick * sb;
+            const double ca = ma + snr * sa, cb = mb + snr * sb;
+            ws.tablet[int64_t(f) * (n_bins + 1) + t1] = SegF{float(ka), float(kb), float(ca), float(cb)};
+            scale = fmax(scale, fmax(fabs(ka) + fabs(kb), fabs(ca) + fabs(cb)));
+        }
+    }
+    if (ws.tolf) {
+        // A line evaluated in float32 from its rounded coefficients is within
+        // 2^-23 (|a| + |b|) of the exact threshold (0 <= frac < 1, one fma),
+        // so a value whose float32 compare could differ from the exact one
+        // lies within that of the float32 threshold; pixels within 1e-6 of
+        // the frame's largest |a| + |b| are decided again in float64.
+        __shared__ double red[kTableBlock];
+        red[tid] = scale;
+        __syncthreads();
+        for (int off = kTableBlock / 2; off > 0; off >>= 1) {
+            if (tid < off) red[tid] = fmax(red[tid], red[tid + off]);
+            __syncthreads();
+        }
+        if (tid == 0) ws.tolf[f] = float(1e-6 * red[0]) + 1e-30f;
     }
     if (tid == 0) {
         if (n_kept) n_kept[f] = 0;
@@ -249,6 +282,19 @@ __device__ inline uint8_t pixel_bits_fast(float x, float frac, const SegF &sg, f
     const float tol = 1e-5f * (fabsf(x) + fabsf(sg.a) + fabsf(sg.b) + fabsf(sg.c) + fabsf(sg.d) + se) + 1e-30f;
     const bool near = fabsf(d - tk) <= tol || fabsf(d - tc) <= tol;
     const uint32_t bits = kValid | (d > tk ? kKeep : 0u) | (d >= tc ? kCand : 0u);
+    return uint8_t(valid ? (near ? uint32_t(kUndecided) : bits) : 0u);
+}
+
+// The same decisions from the threshold lines of a noise-free background:
+// float32 compares against thresholds whose float32 evaluation lies within
+// tol of the exact ones (see k_profile_table); a value within tol of either
+// threshold is kUndecided.
+__device__ inline uint8_t pixel_bits_lines(float x, float frac, const SegF &tl, float tol) {
+    const bool valid = frac == frac && __builtin_isfinite(x);
+    const float tk = fmaf(tl.b, frac, tl.a);
+    const float tc = fmaf(tl.d, frac, tl.c);
+    const bool near = fabsf(x - tk) <= tol || fabsf(x - tc) <= tol;
+    const uint32_t bits = kValid | (x > tk ? kKeep : 0u) | (x >= tc ? kCand : 0u);
     return uint8_t(valid ? (near ? uint32_t(kUndecided) : bits) : 0u);
 }
 
@@ -355,7 +401,7 @@ __device__ inline bool patch_is_peak(const float *v_s, const uint8_t *b_s, int e
     return best && count >= min_count;
 }
 
-template <int kStageSlots, int kH>
+template <int kStageSlots, int kH, bool LINES>
 __global__ __launch_bounds__(kStencilBlock) void k_pixel_state(StateArgs a) {
     extern __shared__ unsigned char lds[];
     const int h = a.half;
@@ -456,7 +502,8 @@ __global__ __launch_bounds__(kStencilBlock) void k_pixel_state(StateArgs a) {
         uint8_t *b_s = b_base + ((f - f0) & 1) * RN;
         uint8_t bv[kStageSlots];
         {
-            const __amdgpu_buffer_rsrc_t rt = buffer_rsrc(a.ws.tablef + int64_t(f) * (a.n_bins + 1), table_bytes);
+            const SegF *tbl = LINES ? a.ws.tablet : a.ws.tablef;
+            const __amdgpu_buffer_rsrc_t rt = buffer_rsrc(tbl + int64_t(f) * (a.n_bins + 1), table_bytes);
             SegF sg[kStageSlots];
 #pragma unroll
             for (int k = 0; k < kStageSlots; ++k) {
@@ -465,9 +512,15 @@ __global__ __launch_bounds__(kStencilBlock) void k_pixel_state(StateArgs a) {
                 const auto q = __builtin_amdgcn_raw_buffer_load_b128(rt, int(toff[k]), 0, 0);
                 __builtin_memcpy(&sg[k], &q, sizeof(SegF));
             }
+            if constexpr (LINES) {
+                const float tol = a.ws.tolf[f];
 #pragma unroll
-            for (int k = 0; k < kStageSlots; ++k) bv[k] = pixel_bits_fast(xv[k], frac[k], sg[k], a.noise2f, a.n_pick_f,
-                                                                          a.snr_f);
+                for (int k = 0; k < kStageSlots; ++k) bv[k] = pixel_bits_lines(xv[k], frac[k], sg[k], tol);
+            } else {
+#pragma unroll
+                for (int k = 0; k < kStageSlots; ++k)
+                    bv[k] = pixel_bits_fast(xv[k], frac[k], sg[k], a.noise2f, a.n_pick_f, a.snr_f);
+            }
         }
         // pixels within rounding of a threshold, in float64 (rare; the
         // float32 table entries are no longer live here)
@@ -1032,7 +1085,7 @@ extern "C" int ss_classify(const float *frames, const uint8_t *mask, int32_t n_f
     Workspace ws = carve(workspace, n_frames, n_pix, radial->n_bins);
     k_profile_table<<<dim3(uint32_t(n_frames)), kTableBlock, 0, stream>>>(
         profile->mean, profile->std, profile->n_members, radial->n_bins, ws, tiles, keep ? n_kept : nullptr,
-        pk ? n_peaks : nullptr);
+        pk ? n_peaks : nullptr, double(p->n_pick), double(p->snr));
     SS_RETURN_IF_LAUNCH_FAILED();
     if (tiles == 0) return SS_OK;
     {
@@ -1063,12 +1116,21 @@ extern "C" int ss_classify(const float *frames, const uint8_t *mask, int32_t n_f
         if (items == 0) return SS_OK;
         if (items > (int64_t(1) << 31)) return SS_ESIZE;
         const dim3 grid(uint32_t(8 * ((items + 7) / 8)));
-        // staging registers sized to the halo; patches 1, 3 and 5 unrolled
-        if (h == 0) k_pixel_state<stage_slots(0), 0><<<grid, kStencilBlock, lds, stream>>>(sa);
-        else if (h == 1) k_pixel_state<stage_slots(1), 1><<<grid, kStencilBlock, lds, stream>>>(sa);
-        else if (h == 2) k_pixel_state<stage_slots(2), 2><<<grid, kStencilBlock, lds, stream>>>(sa);
-        else if (h <= 4) k_pixel_state<stage_slots(4), -1><<<grid, kStencilBlock, lds, stream>>>(sa);
-        else k_pixel_state<stage_slots(SS_MAX_PATCH / 2), -1><<<grid, kStencilBlock, lds, stream>>>(sa);
+        // staging registers sized to the halo; patches 1, 3 and 5 unrolled;
+        // threshold lines when there is no noise level
+        if (p->noise == 0.0f) {
+            if (h == 0) k_pixel_state<stage_slots(0), 0, true><<<grid, kStencilBlock, lds, stream>>>(sa);
+            else if (h == 1) k_pixel_state<stage_slots(1), 1, true><<<grid, kStencilBlock, lds, stream>>>(sa);
+            else if (h == 2) k_pixel_state<stage_slots(2), 2, true><<<grid, kStencilBlock, lds, stream>>>(sa);
+            else if (h <= 4) k_pixel_state<stage_slots(4), -1, true><<<grid, kStencilBlock, lds, stream>>>(sa);
+            else k_pixel_state<stage_slots(SS_MAX_PATCH / 2), -1, true><<<grid, kStencilBlock, lds, stream>>>(sa);
+        } else {
+            if (h == 0) k_pixel_state<stage_slots(0), 0, false><<<grid, kStencilBlock, lds, stream>>>(sa);
+            else if (h == 1) k_pixel_state<stage_slots(1), 1, false><<<grid, kStencilBlock, lds, stream>>>(sa);
+            else if (h == 2) k_pixel_state<stage_slots(2), 2, false><<<grid, kStencilBlock, lds, stream>>>(sa);
+            else if (h <= 4) k_pixel_state<stage_slots(4), -1, false><<<grid, kStencilBlock, lds, stream>>>(sa);
+            else k_pixel_state<stage_slots(SS_MAX_PATCH / 2), -1, false><<<grid, kStencilBlock, lds, stream>>>(sa);
+        }
         SS_RETURN_IF_LAUNCH_FAILED();
     }
 
@@ -1206,7 +1268,7 @@ extern "C" int ss_densify(const uint32_t *kept_index, const float *kept_value, i
     q += align256(size_t(n_frames) * size_t(radial->n_bins + 1) * sizeof(SegF));
     ws.table = reinterpret_cast<Seg *>(q);
     k_profile_table<<<dim3(uint32_t(n_frames)), kTableBlock, 0, stream>>>(
-        profile->mean, profile->std, profile->n_members, radial->n_bins, ws, 0, nullptr, nullptr);
+        profile->mean, profile->std, profile->n_members, radial->n_bins, ws, 0, nullptr, nullptr, 0.0, 0.0);
     SS_RETURN_IF_LAUNCH_FAILED();
 
     DenseArgs a;
