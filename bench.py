@@ -562,6 +562,9 @@ def main():
     ap.add_argument("--workers", type=int, default=0,
                     help="input-generation processes (default: up to 16); 1 generates in-process, "
                          "no fork, as runs under a profiler need")
+    ap.add_argument("--inputs-cache", default="",
+                    help="a .npy file holding the raw frames: read when it exists, written otherwise (several "
+                         "profiler passes over the same inputs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 1 GiB device copy (a known-size reference for HBM counters)")
     args = ap.parse_args()
@@ -572,7 +575,13 @@ def main():
 
     t0 = time.perf_counter()
     workers = args.workers if args.workers > 0 else min(16, os.cpu_count() or 1)
-    raw_np = make_inputs(args.frames, workers)
+    if args.inputs_cache and os.path.exists(args.inputs_cache):
+        raw_np = np.load(args.inputs_cache)
+        assert raw_np.shape == (args.frames, synth.JUNGFRAU4M.n_pix) and raw_np.dtype == np.uint16
+    else:
+        raw_np = make_inputs(args.frames, workers)
+        if args.inputs_cache:
+            np.save(args.inputs_cache, raw_np)
     train_np = make_training(args.train_frames, workers)
     uneven_np, rings_np = make_extra(workers, not args.no_batched, not args.no_serve)
     print(f"# inputs: {args.frames} frames + {args.train_frames} training frames in "
