@@ -305,6 +305,12 @@ __device__ inline void load_state(const double *state, double (&s)[NSUM]) {
 // so every round makes progress.
 constexpr int kRemCap = kWave;
 
+// Removal lists the planning wave reads together per LDS round trip.
+#ifndef SS_CLIP_LIST_GROUP
+#define SS_CLIP_LIST_GROUP 4
+#endif
+constexpr int kListGroup = SS_CLIP_LIST_GROUP;
+
 enum { R_W = 0, R_WD, R_W2, R_W2D, R_W2D2, NREM };
 
 // Per-wave sums of the first evaluation (around the wave's own mean).
@@ -842,12 +848,26 @@ __device__ __forceinline__ void clip_body(const ClipArgs &a, int g, int bin) {
                 const int f = wid + j * NW;
                 if (f >= FB || !ctl[f].go) continue;
                 const double Kc = ctl[f].K;
-                for (int w = 0; w < NW; ++w) {
-                    const int cnt = cnt_s[w][f];
-                    n_removed[j] += cnt;
-                    if (lane < cnt) {
-                        const float2 x = rem_s[w][f][lane];
-                        add_removed(r[j], double(x.x), double(x.y) - Kc);
+                // kListGroup lists at a time: their counts and this lane's
+                // entries are read together (one LDS round trip), then added
+                // in list order; a lane past a list's end adds zeros, which
+                // leaves the sums exactly as they were
+                constexpr int LG = NW < kListGroup ? NW : kListGroup;
+                static_assert(NW % LG == 0, "whole groups of lists");
+#pragma unroll 1
+                for (int w0 = 0; w0 < NW; w0 += LG) {
+                    int cnt[LG];
+                    float2 x[LG];
+#pragma unroll
+                    for (int u = 0; u < LG; ++u) {
+                        cnt[u] = cnt_s[w0 + u][f];
+                        x[u] = rem_s[w0 + u][f][lane];
+                    }
+#pragma unroll
+                    for (int u = 0; u < LG; ++u) {
+                        n_removed[j] += cnt[u];
+                        const bool in = lane < cnt[u];
+                        add_removed(r[j], in ? double(x[u].x) : 0.0, in ? double(x[u].y) - Kc : 0.0);
                     }
                 }
                 if (again) continue;
