@@ -706,16 +706,16 @@ __device__ __forceinline__ void clip_body(const ClipArgs &a, int g, int bin) {
     if (tid < FB) {
         const int f = tid;
         double sw = 0.0, sv = 0.0;
-        // two waves' sums per LDS round trip (not fully unrolled: one
+        // four waves' sums per LDS round trip (not fully unrolled: one
         // thread, and the whole table would fill its registers)
-#pragma unroll 2
+#pragma unroll 4
         for (int w = 0; w < NW; ++w) {
             sw += wstat[f][w][W_W];
             sv += wstat[f][w][W_W] * wstat[f][w][W_MEAN] + wstat[f][w][W_WD];
         }
         const double Kf = sw > 0.0 ? sv / sw : 0.0;
         double st[NSUM] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-#pragma unroll 2
+#pragma unroll 4
         for (int w = 0; w < NW; ++w) {
             const double *x = wstat[f][w];
             const double D = x[W_MEAN] - Kf;
