@@ -641,12 +641,16 @@ __device__ __forceinline__ void clip_body(const ClipArgs &a, int g, int bin) {
                 SS_V(f, e) = ok ? x : __builtin_nanf("");
             }
         }
-        // this wave's mean of each frame, known to all its lanes
+        // this wave's mean of each frame, known to all its lanes (the
+        // member counts summed as float64, exact)
+#pragma unroll
+        for (int f = 0; f < FB; ++f) t[3 * f + 2] = double(n_ok[f]);
+        wave_sum_last_n(t);
 #pragma unroll
         for (int f = 0; f < FB; ++f) {
-            t[3 * f + 0] = wave_sum(t[3 * f + 0]);
-            t[3 * f + 1] = wave_sum(t[3 * f + 1]);
-            t[3 * f + 2] = double(wave_sum(n_ok[f]));
+            t[3 * f + 0] = readlane(t[3 * f + 0], kWave - 1);
+            t[3 * f + 1] = readlane(t[3 * f + 1], kWave - 1);
+            t[3 * f + 2] = readlane(t[3 * f + 2], kWave - 1);
             K[f] = t[3 * f] > 0.0 ? t[3 * f + 1] / t[3 * f] : 0.0;
             if (lane == kWave - 1) {
                 wstat[f][wid][W_W] = t[3 * f];
@@ -686,8 +690,7 @@ __device__ __forceinline__ void clip_body(const ClipArgs &a, int g, int bin) {
                 t[4 * f + 3] = fma(wd, wd, t[4 * f + 3]);
             }
         }
-#pragma unroll
-        for (int q = 0; q < 4 * FB; ++q) t[q] = wave_sum_last(t[q]);
+        wave_sum_last_n(t);
         if (lane == kWave - 1) {
 #pragma unroll
             for (int f = 0; f < FB; ++f) {
@@ -872,8 +875,7 @@ __device__ __forceinline__ void clip_body(const ClipArgs &a, int g, int bin) {
                     }
                 }
                 if (again) continue;
-#pragma unroll
-                for (int q = 0; q < NREM; ++q) r[j][q] = wave_sum_last(r[j][q]);
+                wave_sum_last_n(r[j]);
                 if (lane == kWave - 1) {
                     double sv[NSUM];
                     load_state(state[f], sv);

@@ -53,6 +53,29 @@ __device__ inline double wave_sum_last(double x) {
     return x;
 }
 
+// wave_sum_last of N values, taken stage by stage over groups of up to
+// five of them so that their dependency chains overlap (each result is the
+// same as alone; larger groups would hold more registers for the moves).
+template <int N>
+__device__ inline void wave_sum_last_n(double (&x)[N]) {
+    constexpr int G = 5;
+#pragma unroll
+    for (int k0 = 0; k0 < N; k0 += G) {
+#pragma unroll
+        for (int k = k0; k < N && k < k0 + G; ++k) x[k] += dpp_move<0xB1>(x[k]);
+#pragma unroll
+        for (int k = k0; k < N && k < k0 + G; ++k) x[k] += dpp_move<0x4E>(x[k]);
+#pragma unroll
+        for (int k = k0; k < N && k < k0 + G; ++k) x[k] += dpp_move<0x141>(x[k]);
+#pragma unroll
+        for (int k = k0; k < N && k < k0 + G; ++k) x[k] += dpp_move<0x140>(x[k]);
+#pragma unroll
+        for (int k = k0; k < N && k < k0 + G; ++k) x[k] += dpp_bcast<0x142, 0xA>(x[k]);
+#pragma unroll
+        for (int k = k0; k < N && k < k0 + G; ++k) x[k] += dpp_bcast<0x143, 0xC>(x[k]);
+    }
+}
+
 // The same total, given to every lane.
 __device__ inline double wave_sum(double x) { return readlane(wave_sum_last(x), kWave - 1); }
 
