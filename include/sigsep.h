@@ -19,7 +19,12 @@
  * - Return value: SS_OK (0), or a negative code detected on the host before
  *   anything was enqueued (SS_EINVAL, SS_ESIZE), or SS_EHIP when the HIP
  *   runtime reported a launch error.  ss_strerror() names a code.
- * - Frames are row-major [n_frames][n_pix] with pixel index y * width + x.
+ * - Frames are [n_frames][words] float32, row-major (words = n_pix, pixel
+ *   index y * width + x) unless a call names a tiled layout (ss_layout):
+ *   ss_correct_tiled writes one, ss_sigma_clip reads whatever layout its
+ *   CSR indices address, and the ss_classify family reads the layout its
+ *   ss_radial names.  Pixel indices in outputs (kept pixels, peaks) are
+ *   always y * width + x.
  * - Masks are uint8, nonzero = masked.  A frame value that is not finite
  *   (NaN/Inf, e.g. an invalid gain code) marks that pixel masked in that
  *   frame only.
@@ -140,6 +145,28 @@ typedef struct {
 } ss_profile;
 
 /*
+ * Frame layout.  Row-major frames (tile_w = tile_h = 0) hold pixel (y, x) at
+ * word y * width + x.  A tiled layout cuts the frame into tiles of tile_w x
+ * tile_h pixels (powers of two, 4 <= tile_w <= 64, 1 <= tile_h <= 64),
+ * tiles row-major, pixels row-major inside a tile: pixel (y, x) sits at word
+ *   ((y / tile_h) * tiles_x + x / tile_w) * tile_w * tile_h
+ *     + (y % tile_h) * tile_w + x % tile_w,   tiles_x = ceil(width / tile_w),
+ * and a frame holds tiles_x * ceil(height / tile_h) * tile_w * tile_h words
+ * (ss_layout_words); words of partial tiles past the image edge are NaN.
+ * With 8 x 4 tiles (one 128-byte line per tile) the pixels of a thin ring
+ * that a line holds are neighbours in two dimensions, not along one image
+ * row, so the CSR gathers of the regrouping (Sec. 2.2) touch about half as
+ * many lines.  Frames in a tiled layout go with a CSR whose indices are word
+ * offsets in it (ss_csr_relayout) and an ss_radial naming the layout.
+ */
+typedef struct {
+    int32_t height;
+    int32_t width;
+    int32_t tile_w;
+    int32_t tile_h;
+} ss_layout;
+
+/*
  * Radial position of every pixel for the background lookup of Sec. 3 ("the
  * distance to the centre of every pixel").  Bins are uniform: centre of bin r
  * = centre0 + r * width.  rcoord[i] packs the interval t (bin centre t <=
@@ -153,6 +180,8 @@ typedef struct {
     double centre0;
     double width;
     const uint32_t *rcoord; /* [dev] [n_pix] */
+    int32_t tile_w;         /* layout of the frames read with it (ss_layout): */
+    int32_t tile_h;         /* 0, 0 for row-major frames                     */
 } ss_radial;
 
 /* Peak record of Sec. 4: centroid (pixel units, centres at +0.5), sum of
@@ -207,6 +236,34 @@ int ss_csr_schedule(const int64_t *indptr, int32_t n_bins, int32_t *bin_order, i
 int32_t ss_class_rows(int32_t c);
 
 /*
+ * ss_layout_words [host] -- words per frame of a layout (height * width for
+ * row-major frames), or a negative code: SS_EINVAL for a null layout,
+ * SS_ESIZE for sizes out of range or tiles that are not as ss_layout states.
+ */
+int64_t ss_layout_words(const ss_layout *layout);
+
+/*
+ * ss_csr_relayout [host] -- turn the pixel indices of a CSR from
+ * ss_build_csr (layout height x width) into word offsets of the layout and
+ * sort every row by offset, moving the weights along (a row's sums are then
+ * taken in that order: the same members, rounding of the float64 sums
+ * aside).  indptr [host] [n_bins + 1]; indices and weight [host] [nnz],
+ * rewritten in place.  Errors: SS_EINVAL (null pointer, an index outside
+ * the image, a row that does not ascend in indptr), SS_ESIZE (layout).
+ */
+int ss_csr_relayout(const ss_layout *layout, int32_t n_bins, const int64_t *indptr, int32_t *indices,
+                    float *weight);
+
+/*
+ * ss_layout_scatter [host] -- a per-pixel float array (row-major, height x
+ * width) rewritten in a layout: dst [host] [ss_layout_words] receives
+ * src[y * width + x] at the word of pixel (y, x) and fill elsewhere (for
+ * the norm array of ss_sigma_clip on tiled frames).  Errors: SS_EINVAL,
+ * SS_ESIZE (layout).
+ */
+int ss_layout_scatter(const ss_layout *layout, const float *src, float fill, float *dst);
+
+/*
  * ss_radial_coords [host] -- rcoord [host] [n_pix] of the pixel-centre
  * angles for the bins of ss_build_csr (same geometry, n_bins and tth_max);
  * masked pixels (mask may be NULL) get SS_RC_MASKED.  *centre0 and *width
@@ -254,6 +311,21 @@ int ss_correct_indexed(const uint16_t *ring, int64_t ring_frames, const int64_t 
                        const float *norm, float *out, int64_t *n_invalid, hipStream_t stream);
 
 /*
+ * ss_correct_tiled / ss_correct_indexed_tiled -- ss_correct /
+ * ss_correct_indexed writing the corrected frames in a layout: raw words,
+ * pedestal, gain and norm stay row-major over layout->height x
+ * layout->width pixels; out [dev] float [n_frames][ss_layout_words(layout)],
+ * NaN at the words past the image edge.  Errors: those of ss_correct;
+ * SS_EINVAL for a null layout, SS_ESIZE for a layout ss_layout_words
+ * refuses.
+ */
+int ss_correct_tiled(const uint16_t *raw, int32_t n_frames, const ss_layout *layout, const float *pedestal,
+                     const float *gain, const float *norm, float *out, int64_t *n_invalid, hipStream_t stream);
+int ss_correct_indexed_tiled(const uint16_t *ring, int64_t ring_frames, const int64_t *frame_index,
+                             int32_t n_frames, const ss_layout *layout, const float *pedestal, const float *gain,
+                             const float *norm, float *out, int64_t *n_invalid, hipStream_t stream);
+
+/*
  * ss_integrate_csr -- azimuthal average with uncertainties (Sec. 2.2, eqs. avg
  * to sem2), no clipping: ss_sigma_clip with max_iter forced to 0.
  */
@@ -289,11 +361,14 @@ int ss_sigma_clip_batches(const ss_clip_batch *batches, int32_t n_batches,
  * members with |v - mean| > n * std (strict; n = cutoff or Chauvenet's value
  * for the current size); the loop stops at the first pass that removes
  * nothing.  The profile holds the statistics of the final set.
- *   frames [dev] float [n_frames][csr->n_pix] (corrected intensities v)
- *   norm   [dev] float [n_pix] or NULL; used only by the Poisson and hybrid
- *          models, whose pixel variance is (max(v * norm, 0) + dark_var) /
- *          norm^2 in units of v
- *   mask   [dev] uint8 [n_pix] or NULL (in addition to the CSR's own mask)
+ *   frames [dev] float [n_frames][csr->n_pix] (corrected intensities v):
+ *          csr->n_pix words per frame, in whatever layout the CSR indices
+ *          address (pixel indices, or word offsets after ss_csr_relayout)
+ *   norm   [dev] float [csr->n_pix] or NULL, indexed like the frames; used
+ *          only by the Poisson and hybrid models, whose pixel variance is
+ *          (max(v * norm, 0) + dark_var) / norm^2 in units of v
+ *   mask   [dev] uint8 [csr->n_pix] or NULL, indexed like the frames (in
+ *          addition to the CSR's own mask)
  *   csr, params, out: [host] structs; their arrays are [dev]
  * Errors: SS_EINVAL, SS_ESIZE (n_bins > SS_MAX_BINS, max_iter out of range),
  * SS_EHIP.
@@ -328,7 +403,9 @@ size_t ss_classify_workspace(int32_t n_frames, int64_t n_pix, int32_t n_bins);
  * x_j + 0.5) / sum w_j.  peaks [dev] [n_frames][peak_capacity] in ascending
  * index; n_peaks [dev] int64 [n_frames] (true count).
  * Either output group may be disabled by passing NULL for all its pointers.
- *   frames [dev] float [n_frames][height * width]; mask [dev] or NULL
+ *   frames [dev] float [n_frames][words], words = ss_layout_words of
+ *     (height, width, radial->tile_w, radial->tile_h): height * width for
+ *     row-major frames; mask [dev] or NULL
  *   radial, profile, params: [host] structs with [dev] arrays
  *   workspace [dev] >= ss_classify_workspace(...) bytes
  * Errors: SS_EINVAL, SS_ESIZE (workspace too small, capacities < 0,
@@ -418,7 +495,8 @@ size_t ss_densify_workspace(int32_t n_frames, int32_t n_bins);
  *   mask [dev] uint8 [n_pix] or NULL; radial, profile: [host] structs with
  *     [dev] arrays (profile mean, std, n_members used)
  *   noise [host] or NULL (noise free)
- *   dense [dev] float [n_frames][n_pix], written entirely
+ *   dense [dev] float [n_frames][n_pix], row-major (the tile fields of
+ *     radial are not used), written entirely
  *   workspace [dev] >= ss_densify_workspace(n_frames, radial->n_bins) bytes
  * Errors: SS_EINVAL (null pointers, NaN trunc), SS_ESIZE (sizes,
  * workspace), SS_EHIP.

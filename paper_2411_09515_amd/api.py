@@ -73,7 +73,7 @@ def _profile_args(prof, F, nb, name="profile", keys=None):
 def _frames_arg(frames, geom, name="frames"):
     if not isinstance(frames, torch.Tensor) or frames.dim() != 2:
         raise ValueError(f"{name}: expected a [F, n_pix] tensor")
-    _arg(frames, name, torch.float32, (None, geom.n_pix))
+    _arg(frames, name, torch.float32, (None, geom.frame_words))
     return frames.shape[0]
 
 
@@ -145,13 +145,36 @@ def build_csr_host(height, width, pixel_m, dist_m, centre_row, centre_col, n_bin
 
 class Geometry:
     """Device-resident detector geometry: CSR with weights c * norm, packed
-    radial coordinates, normalisation and static mask."""
+    radial coordinates, normalisation and static mask.
+
+    ``tile=(tile_w, tile_h)`` selects a tiled layout for the corrected
+    frames (see ss_layout): ``correct(..., geom=)`` writes it, the CSR
+    indices address it and classification reads it; ``frame_words`` is the
+    frame length in that layout (``n_pix`` for row-major frames)."""
 
     def __init__(self, height, width, pixel_m, dist_m, centre_row, centre_col, n_bins, split="bbox",
-                 mask=None, norm=None, device="cuda"):
+                 mask=None, norm=None, device="cuda", tile=None):
         h = build_csr_host(height, width, pixel_m, dist_m, centre_row, centre_col, n_bins, split, mask, norm)
         self.height, self.width, self.n_bins = int(height), int(width), int(n_bins)
         self.n_pix = self.height * self.width
+        self.tile = None if tile is None else (int(tile[0]), int(tile[1]))
+        self.frame_words = self.n_pix
+        clip_norm = None if norm is None else np.ascontiguousarray(norm, dtype=np.float32).reshape(-1)
+        if self.tile is not None:
+            L = B.lib()
+            lay = self.layout_c()
+            words = L.ss_layout_words(ctypes.byref(lay))
+            if words < 0:
+                raise ValueError(f"tile {tile}: {B.strerror(int(words))}")
+            self.frame_words = int(words)
+            h = dict(h, indices=h["indices"].copy(), weight=h["weight"].copy())
+            B.check("ss_csr_relayout", L.ss_csr_relayout(ctypes.byref(lay), self.n_bins, _host_ptr(h["indptr"]),
+                                                         _host_ptr(h["indices"]), _host_ptr(h["weight"])))
+            if clip_norm is not None:
+                tiled = np.empty(self.frame_words, dtype=np.float32)
+                B.check("ss_layout_scatter", L.ss_layout_scatter(ctypes.byref(lay), _host_ptr(clip_norm), 1.0,
+                                                                 _host_ptr(tiled)))
+                clip_norm = tiled
         self.nnz, self.max_row, self.tth_max = h["nnz"], h["max_row"], h["tth_max"]
         self.centre0, self.bin_width = h["centre0"], h["width"]
         dev = torch.device(device)
@@ -165,26 +188,33 @@ class Geometry:
         self.scheduled = True
         self.norm = None if norm is None else torch.from_numpy(
             np.array(norm, dtype=np.float32).reshape(-1)).to(dev)
+        # the norm indexed like the frames (the clip's Poisson variance)
+        self.clip_norm = self.norm if self.tile is None or clip_norm is None else torch.from_numpy(clip_norm).to(dev)
         self.mask = None if mask is None else torch.from_numpy(
             np.array(mask, dtype=np.uint8).reshape(-1)).to(dev)
         self.host = h
 
     @classmethod
-    def from_scene(cls, geom, mask=None, norm=None, device="cuda"):
+    def from_scene(cls, geom, mask=None, norm=None, device="cuda", tile=None):
         """Geometry of a ``synth.Geometry`` description."""
         return cls(geom.height, geom.width, geom.pixel_m, geom.dist_m, geom.centre_row, geom.centre_col,
-                   geom.n_bins, geom.split, mask, norm, device)
+                   geom.n_bins, geom.split, mask, norm, device, tile)
+
+    def layout_c(self) -> B.Layout:
+        tw, th = self.tile if self.tile is not None else (0, 0)
+        return B.Layout(self.height, self.width, tw, th)
 
     def csr(self) -> B.Csr:
         """The C struct; with ``scheduled`` the clip launches per row-length class."""
         counts = (ctypes.c_int32 * B.SS_N_CLASSES)(*[int(c) for c in self.class_count])
         shape = (ctypes.c_int32 * B.SS_N_CLASSES)(*[int(c) for c in self.shape])
-        return B.Csr(self.n_bins, self.max_row, self.n_pix, self.nnz, self.indptr.data_ptr(),
+        return B.Csr(self.n_bins, self.max_row, self.frame_words, self.nnz, self.indptr.data_ptr(),
                      self.indices.data_ptr(), self.weight.data_ptr(),
                      self.bin_order.data_ptr() if self.scheduled else None, counts, shape)
 
     def radial(self) -> B.Radial:
-        return B.Radial(self.n_bins, self.centre0, self.bin_width, self.rcoord.data_ptr())
+        tw, th = self.tile if self.tile is not None else (0, 0)
+        return B.Radial(self.n_bins, self.centre0, self.bin_width, self.rcoord.data_ptr(), tw, th)
 
     @property
     def bin_centres(self) -> np.ndarray:
@@ -193,11 +223,16 @@ class Geometry:
 
 # -- correction ------------------------------------------------------------------------
 
-def correct(raw, pedestal, gain, norm=None, out=None, n_invalid=None):
-    """Raw Jungfrau words [F, N] uint16 -> corrected intensity [F, N] float32."""
+def correct(raw, pedestal, gain, norm=None, out=None, n_invalid=None, geom=None):
+    """Raw Jungfrau words [F, N] uint16 -> corrected intensity [F, N] float32,
+    or [F, geom.frame_words] in the layout of a tiled ``geom``."""
     if not isinstance(raw, torch.Tensor) or raw.dim() != 2:
         raise ValueError("raw: expected a [F, N] tensor of 16-bit words")
     F, N = raw.shape
+    if geom is not None and geom.tile is not None:
+        if N != geom.n_pix:
+            raise ValueError(f"raw: expected {geom.n_pix} pixels per frame, got {N}")
+        return _correct_tiled(raw, None, pedestal, gain, norm, out, n_invalid, geom)
     _arg(raw, "raw", (torch.uint16, torch.int16), (F, N))
     _arg(pedestal, "pedestal", torch.float32, (3, N))
     _arg(gain, "gain", torch.float32, (3, N))
@@ -215,13 +250,18 @@ def correct(raw, pedestal, gain, norm=None, out=None, n_invalid=None):
     return out, n_invalid
 
 
-def correct_indexed(ring, frame_index, pedestal, gain, norm=None, out=None, n_invalid=None):
+def correct_indexed(ring, frame_index, pedestal, gain, norm=None, out=None, n_invalid=None, geom=None):
     """Correction of ring frames picked by a device index: ring [K, N] of
-    16-bit words, frame_index [F] int64 on the device -> out [F, N] float32
-    (an index outside the ring gives an all-invalid frame)."""
+    16-bit words, frame_index [F] int64 on the device -> out [F, N] float32,
+    or [F, geom.frame_words] for a tiled ``geom`` (an index outside the ring
+    gives an all-invalid frame)."""
     if not isinstance(ring, torch.Tensor) or ring.dim() != 2:
         raise ValueError("ring: expected a [K, N] tensor of 16-bit words")
     K, N = ring.shape
+    if geom is not None and geom.tile is not None:
+        if N != geom.n_pix:
+            raise ValueError(f"ring: expected {geom.n_pix} pixels per frame, got {N}")
+        return _correct_tiled(ring, frame_index, pedestal, gain, norm, out, n_invalid, geom)
     _arg(ring, "ring", (torch.uint16, torch.int16), (K, N))
     _arg(frame_index, "frame_index", torch.int64, (None,))
     F = frame_index.shape[0]
@@ -238,6 +278,35 @@ def correct_indexed(ring, frame_index, pedestal, gain, norm=None, out=None, n_in
     _arg(n_invalid, "n_invalid", torch.int64, (F,))
     B.check("ss_correct_indexed", B.lib().ss_correct_indexed(_p(ring), K, _p(frame_index), F, N, _p(pedestal),
                                                              _p(gain), _p(norm), _p(out), _p(n_invalid), _stream()))
+    return out, n_invalid
+
+
+def _correct_tiled(raw, frame_index, pedestal, gain, norm, out, n_invalid, geom):
+    """ss_correct_tiled / ss_correct_indexed_tiled (raw or ring [K, N])."""
+    K, N = raw.shape
+    _arg(raw, "raw", (torch.uint16, torch.int16), (K, N))
+    if frame_index is not None:
+        _arg(frame_index, "frame_index", torch.int64, (None,))
+    F = K if frame_index is None else frame_index.shape[0]
+    if pedestal is None or gain is None:
+        raise ValueError("pedestal and gain are required")
+    _arg(pedestal, "pedestal", torch.float32, (3, N))
+    _arg(gain, "gain", torch.float32, (3, N))
+    _arg(norm, "norm", torch.float32, (N,))
+    if out is None:
+        out = torch.empty((F, geom.frame_words), dtype=torch.float32, device=raw.device)
+    if n_invalid is None:
+        n_invalid = torch.empty(F, dtype=torch.int64, device=raw.device)
+    _arg(out, "out", torch.float32, (F, geom.frame_words))
+    _arg(n_invalid, "n_invalid", torch.int64, (F,))
+    lay = geom.layout_c()
+    if frame_index is None:
+        B.check("ss_correct_tiled", B.lib().ss_correct_tiled(_p(raw), F, ctypes.byref(lay), _p(pedestal), _p(gain),
+                                                             _p(norm), _p(out), _p(n_invalid), _stream()))
+    else:
+        B.check("ss_correct_indexed_tiled", B.lib().ss_correct_indexed_tiled(
+            _p(raw), K, _p(frame_index), F, ctypes.byref(lay), _p(pedestal), _p(gain), _p(norm), _p(out),
+            _p(n_invalid), _stream()))
     return out, n_invalid
 
 
@@ -260,15 +329,16 @@ def profile_c(prof) -> B.Profile:
 
 
 def sigma_clip(frames, geom: Geometry, params: Params, out=None, norm=None, mask=None, integrate_only=False):
-    """Per-bin clipped profile of frames [F, N] float32 (corrected intensity)."""
+    """Per-bin clipped profile of frames [F, geom.frame_words] float32
+    (corrected intensity; norm and mask, if given, indexed like the frames)."""
     F = _frames_arg(frames, geom)
-    _arg(norm, "norm", torch.float32, (geom.n_pix,))
-    _arg(mask, "mask", torch.uint8, (geom.n_pix,))
+    _arg(norm, "norm", torch.float32, (geom.frame_words,))
+    _arg(mask, "mask", torch.uint8, (geom.frame_words,))
     if out is None:
         out = new_profile(F, geom.n_bins, frames.device)
     _profile_args(out, F, geom.n_bins, "out")
     if norm is None and params.error_model != "azimuthal":
-        norm = geom.norm
+        norm = geom.clip_norm
     fn = B.lib().ss_integrate_csr if integrate_only else B.lib().ss_sigma_clip
     B.check("ss_sigma_clip", fn(_p(frames), _p(norm), _p(mask), F, ctypes.byref(geom.csr()),
                                 ctypes.byref(params.c()), ctypes.byref(profile_c(out)), _stream()))
@@ -287,7 +357,7 @@ def sigma_clip_batches(batches, params: Params, outs=None):
         _profile_args(out, F, geom.n_bins, f"outs[{i}]")
         csr, prof = geom.csr(), profile_c(out)
         keep += [csr, prof]
-        norm = geom.norm if params.error_model != "azimuthal" else None
+        norm = geom.clip_norm if params.error_model != "azimuthal" else None
         arr[i] = B.ClipBatch(_p(frames).value, None if norm is None else _p(norm).value, frames.shape[0],
                              ctypes.addressof(csr), ctypes.addressof(prof))
     B.check("ss_sigma_clip_batches", B.lib().ss_sigma_clip_batches(arr, len(batches), ctypes.byref(params.c()),
@@ -338,7 +408,7 @@ def integrate(frames, geom: Geometry, params: Params, out=None, norm=None, mask=
 def clip_features(frames, geom: Geometry, norm=None):
     """Surrogate inputs [F, nb, 19] (float32) and unclipped (n, mean, std) [F, nb, 3] (float64)."""
     F = _frames_arg(frames, geom)
-    _arg(norm, "norm", torch.float32, (geom.n_pix,))
+    _arg(norm, "norm", torch.float32, (geom.frame_words,))
     feats = torch.empty((F, geom.n_bins, B.SS_MLP_IN), dtype=torch.float32, device=frames.device)
     stats0 = torch.empty((F, geom.n_bins, 3), dtype=torch.float64, device=frames.device)
     B.check("ss_clip_features", B.lib().ss_clip_features(_p(frames), _p(norm), None, F, ctypes.byref(geom.csr()),
@@ -439,7 +509,7 @@ def sigma_clip_surrogate(frames, geom: Geometry, params: Params, model: Surrogat
     """The clip warm-started by the surrogate; ``state`` [F, nb] int32 receives
     1 (accepted), 0 (no prediction) or -1 (refused, clipped again from scratch)."""
     F = _frames_arg(frames, geom)
-    _arg(norm, "norm", torch.float32, (geom.n_pix,))
+    _arg(norm, "norm", torch.float32, (geom.frame_words,))
     _arg(state, "state", torch.int32, (F, geom.n_bins))
     if out is None:
         out = new_profile(F, geom.n_bins, frames.device)
@@ -722,7 +792,7 @@ class Pipeline:
         self.geom, self.params, self.n_frames = geom, params, n_frames
         self.pedestal, self.gain = pedestal, gain
         self.kept_capacity, self.peak_capacity = kept_capacity, peak_capacity
-        self.frames = torch.empty((n_frames, geom.n_pix), dtype=torch.float32, device=device)
+        self.frames = torch.empty((n_frames, geom.frame_words), dtype=torch.float32, device=device)
         self.n_invalid = torch.empty(n_frames, dtype=torch.int64, device=device)
         self.profile = new_profile(n_frames, geom.n_bins, device)
         self.workspace = new_workspace(n_frames, geom, device)
@@ -734,7 +804,7 @@ class Pipeline:
                         n_peaks=torch.empty(n_frames, dtype=torch.int64, device=device))
 
     def correct(self, raw):
-        return correct(raw, self.pedestal, self.gain, self.geom.norm, self.frames, self.n_invalid)
+        return correct(raw, self.pedestal, self.gain, self.geom.norm, self.frames, self.n_invalid, geom=self.geom)
 
     def separate(self, frames=None):
         frames = self.frames if frames is None else frames

@@ -35,7 +35,8 @@ SS_CLASSIFY_SCRATCH_BYTES = 64 << 20
 
 EXPORTED = (
     "ss_strerror", "ss_version", "ss_build_csr", "ss_csr_schedule", "ss_class_rows", "ss_radial_coords",
-    "ss_correct", "ss_correct_indexed",
+    "ss_layout_words", "ss_csr_relayout", "ss_layout_scatter",
+    "ss_correct", "ss_correct_indexed", "ss_correct_tiled", "ss_correct_indexed_tiled",
     "ss_integrate_csr", "ss_sigma_clip", "ss_classify_workspace", "ss_classify", "ss_classify_noalloc",
     "ss_compress", "ss_peakfind",
     "ss_clip_features", "ss_surrogate_targets", "ss_mlp_forward", "ss_mlp_grad_workspace", "ss_mlp_grad",
@@ -76,7 +77,12 @@ class Profile(ctypes.Structure):
 
 class Radial(ctypes.Structure):
     _fields_ = [("n_bins", ctypes.c_int32), ("centre0", ctypes.c_double), ("width", ctypes.c_double),
-                ("rcoord", ctypes.c_void_p)]
+                ("rcoord", ctypes.c_void_p), ("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32)]
+
+
+class Layout(ctypes.Structure):
+    _fields_ = [("height", ctypes.c_int32), ("width", ctypes.c_int32), ("tile_w", ctypes.c_int32),
+                ("tile_h", ctypes.c_int32)]
 
 
 class Peak(ctypes.Structure):
@@ -115,10 +121,20 @@ def lib():
         L.ss_class_rows.argtypes = [i32]
         L.ss_radial_coords.restype = ctypes.c_int
         L.ss_radial_coords.argtypes = [i32, i32, f64, f64, f64, f64, i32, f64, vp, vp, P(f64), P(f64)]
+        L.ss_layout_words.restype = i64
+        L.ss_layout_words.argtypes = [P(Layout)]
+        L.ss_csr_relayout.restype = ctypes.c_int
+        L.ss_csr_relayout.argtypes = [P(Layout), i32, vp, vp, vp]
+        L.ss_layout_scatter.restype = ctypes.c_int
+        L.ss_layout_scatter.argtypes = [P(Layout), vp, ctypes.c_float, vp]
         L.ss_correct.restype = ctypes.c_int
         L.ss_correct.argtypes = [vp, i32, i64, vp, vp, vp, vp, vp, vp]
         L.ss_correct_indexed.restype = ctypes.c_int
         L.ss_correct_indexed.argtypes = [vp, i64, vp, i32, i64, vp, vp, vp, vp, vp, vp]
+        L.ss_correct_tiled.restype = ctypes.c_int
+        L.ss_correct_tiled.argtypes = [vp, i32, P(Layout), vp, vp, vp, vp, vp, vp]
+        L.ss_correct_indexed_tiled.restype = ctypes.c_int
+        L.ss_correct_indexed_tiled.argtypes = [vp, i64, vp, i32, P(Layout), vp, vp, vp, vp, vp, vp]
         for name in ("ss_integrate_csr", "ss_sigma_clip"):
             fn = getattr(L, name)
             fn.restype = ctypes.c_int

@@ -217,7 +217,8 @@ __global__ __launch_bounds__(kTableBlock) void k_profile_table(
 // ---- classification ----------------------------------------------------------
 
 struct ClassArgs {
-    const float *frames;
+    const float *frames;  // [n_frames][lay.words], in layout lay
+    Layout lay;
     int32_t n_frames;
     const uint8_t *mask;
     const uint32_t *rcoord;
@@ -236,6 +237,14 @@ struct ClassArgs {
     int64_t *n_peaks;
     Workspace ws;
 };
+
+// Word of raster pixel p in a frame of layout L (no division for row-major
+// frames).
+__device__ inline int64_t frame_word(const Layout &L, int64_t p) {
+    if (!L.tiled()) return p;
+    const uint32_t y = uint32_t(p) / uint32_t(L.width);
+    return L.offset(int(y), int(uint32_t(p) - y * uint32_t(L.width)));
+}
 
 __device__ inline void background(uint32_t rc, const Seg *__restrict__ tab, int n_bins, double noise2,
                                   double &mu, double &se) {
@@ -320,7 +329,8 @@ constexpr int kFramesPerBlock = SS_STENCIL_FRAMES;
 constexpr int stage_slots(int h) { return ((kTileH + 2 * h) * (kTileW + 2 * h) + kStencilBlock - 1) / kStencilBlock; }
 
 struct StateArgs {
-    const float *frames;
+    const float *frames;  // [n_frames][lay.words], in layout lay
+    Layout lay;
     const uint32_t *rcoord;
     const uint8_t *mask;
     int32_t n_frames;
@@ -401,8 +411,31 @@ __device__ inline bool patch_is_peak(const float *v_s, const uint8_t *b_s, int e
     return best && count >= min_count;
 }
 
-template <int kStageSlots, int kH, bool LINES>
-__global__ __launch_bounds__(kStencilBlock) void k_pixel_state(StateArgs a) {
+// Region pixel (row-major index in the RH x RW staged region whose top left
+// pixel is (Y0, X0)) of staged slot s, the region's pixels taken tile by
+// tile of a tiled frame layout (tiles of 2^sw x 2^sh, aligned to the
+// frame): the 64 lanes of a wave then load whole tiles, two 128-byte lines
+// for 8 x 4 tiles, instead of one region row that crosses nine.  Tiles cut
+// the region into row groups of whole rows (the first and last may be
+// partial) and each row group into blocks of whole columns; a row group is
+// stored block after block, each block row-major.
+__device__ inline int tile_order_slot(int s, int RW, int RH, int Y0, int X0, int sw, int sh, uint32_t magic) {
+    const int oy = Y0 & ((1 << sh) - 1), ox = X0 & ((1 << sw) - 1);
+    const int r = int((uint32_t(s) * magic) >> 20);       // region row of s in row-major order
+    const int gi = (r + oy) >> sh;                          // its row group (groups hold whole rows)
+    const int r0 = max(0, (gi << sh) - oy), r1 = min(RH, ((gi + 1) << sh) - oy);
+    const int gh = r1 - r0;
+    const int w = s - r0 * RW;                              // position in the row group
+    const int gj = (w / gh + ox) >> sw;                     // block of the row group
+    const int c0 = max(0, (gj << sw) - ox), c1 = min(RW, ((gj + 1) << sw) - ox);
+    const int u = w - c0 * gh;
+    const int gw = c1 - c0;
+    return (r0 + u / gw) * RW + c0 + u % gw;
+}
+
+template <int kStageSlots, int kH, bool LINES, bool TILED>
+__global__ __launch_bounds__(kStencilBlock) __attribute__((amdgpu_waves_per_eu(kH == 0 || kH == 1 ? 8 : 1)))
+void k_pixel_state(StateArgs a) {
     extern __shared__ unsigned char lds[];
     const int h = a.half;
     const int RW = kTileW + 2 * h, RH = kTileH + 2 * h, RN = RW * RH;
@@ -454,18 +487,26 @@ __global__ __launch_bounds__(kStencilBlock) void k_pixel_state(StateArgs a) {
     // masked), its interval's byte offset in a frame's float32 table, and
     // its fraction of the interval (NaN when masked).  Frames hold fewer
     // than 2^29 pixels, so byte offsets fit 32 bits.
+    // With a tiled frame layout, slot k of a thread is region pixel e_k
+    // (tile by tile), kept in the high half of toff[k] (table offsets are
+    // below 2^16 bytes, region indices too); otherwise region pixel
+    // tid + k * kStencilBlock.
     uint32_t voff[kStageSlots], toff[kStageSlots];
     float frac[kStageSlots];
 #pragma unroll
     for (int k = 0; k < kStageSlots; ++k) {
-        const int e = tid + k * kStencilBlock;
+        const int sk = tid + k * kStencilBlock;
+        int e = sk;
+        if constexpr (TILED)
+            e = sk < RN ? tile_order_slot(sk, RW, RH, ty0 - h, tx0 - h, a.lay.sw, a.lay.sh, magic) : RN;
         const int ec = min(e, RN - 1);
         const int r = int((uint32_t(ec) * magic) >> 20);
         const int y = min(max(ty0 - h + r, 0), a.height - 1);
         const int x = min(max(tx0 - h + (ec - r * RW), 0), a.width - 1);
-        voff[k] = (uint32_t(y) * uint32_t(a.width) + uint32_t(x)) * 4u;
+        voff[k] = uint32_t(a.lay.offset(y, x)) * 4u;
         const uint32_t rc = e < RN ? rc_s[e] : SS_RC_MASKED;
         toff[k] = uint32_t(min(int(rc >> SS_RC_FRAC_BITS), a.n_bins)) * uint32_t(sizeof(SegF));
+        if constexpr (TILED) toff[k] |= uint32_t(e) << 16;
         frac[k] = rc == SS_RC_MASKED ? __builtin_nanf("")
                                      : float(rc & ((1u << SS_RC_FRAC_BITS) - 1u)) * (1.0f / float(1u << SS_RC_FRAC_BITS));
     }
@@ -489,11 +530,11 @@ __global__ __launch_bounds__(kStencilBlock) void k_pixel_state(StateArgs a) {
     // so one barrier per frame separates staging from the patch test: a
     // thread stages frame f + 1 only after the barrier of frame f, which
     // every thread reaches after its patch tests of frame f - 1.
-    const uint32_t frame_bytes = uint32_t(a.n_pix) * 4u;
+    const uint32_t frame_bytes = uint32_t(a.lay.words) * 4u;
     const uint32_t table_bytes = uint32_t(a.n_bins + 1) * uint32_t(sizeof(SegF));
     float xv[kStageSlots];
     if (f0 < f1) {
-        const __amdgpu_buffer_rsrc_t rf = buffer_rsrc(a.frames + int64_t(f0) * a.n_pix, frame_bytes);
+        const __amdgpu_buffer_rsrc_t rf = buffer_rsrc(a.frames + int64_t(f0) * a.lay.words, frame_bytes);
 #pragma unroll
         for (int k = 0; k < kStageSlots; ++k) xv[k] = buffer_load_f32(rf, voff[k], 0u);
     }
@@ -509,7 +550,12 @@ __global__ __launch_bounds__(kStencilBlock) void k_pixel_state(StateArgs a) {
             for (int k = 0; k < kStageSlots; ++k) {
                 // (element access on the builtin's vector result is not used:
                 // copying the whole vector out keeps the 16-byte load intact)
-                const auto q = __builtin_amdgcn_raw_buffer_load_b128(rt, int(toff[k]), 0, 0);
+                uint32_t to = toff[k];
+                if constexpr (TILED) {
+                    asm volatile("" : "+v"(to));  // masked here, not held masked across frames
+                    to &= 0xFFFFu;
+                }
+                const auto q = __builtin_amdgcn_raw_buffer_load_b128(rt, int(to), 0, 0);
                 __builtin_memcpy(&sg[k], &q, sizeof(SegF));
             }
             if constexpr (LINES) {
@@ -532,19 +578,28 @@ __global__ __launch_bounds__(kStencilBlock) void k_pixel_state(StateArgs a) {
 #pragma unroll
             for (int k = 0; k < kStageSlots; ++k)
                 if (bv[k] == kUndecided)
-                    bv[k] = pixel_bits(xv[k], rc_s[tid + k * kStencilBlock], false, tab, a.n_bins, a.noise2, a.n_pick,
+                    bv[k] = pixel_bits(xv[k], rc_s[TILED ? int(toff[k] >> 16) : tid + k * kStencilBlock], false, tab,
+                                       a.n_bins, a.noise2, a.n_pick,
                                        a.snr);
         }
 #pragma unroll
         for (int k = 0; k < kStageSlots; ++k) {
-            const int e = tid + k * kStencilBlock;
-            if (k < kStageSlots - 1 || e < RN) {
+            const int sk = tid + k * kStencilBlock;
+            int e = sk;
+            if constexpr (TILED) {
+                // formed here each frame: kept out of the loop, the LDS
+                // addresses of every slot would hold registers of their own
+                uint32_t t = toff[k];
+                asm volatile("" : "+v"(t));
+                e = int(t >> 16);
+            }
+            if (k < kStageSlots - 1 || sk < RN) {
                 v_s[e] = frac[k] == frac[k] ? xv[k] : 0.0f;
                 b_s[e] = bv[k];
             }
         }
         if (f + 1 < f1) {
-            const __amdgpu_buffer_rsrc_t rf = buffer_rsrc(a.frames + int64_t(f + 1) * a.n_pix, frame_bytes);
+            const __amdgpu_buffer_rsrc_t rf = buffer_rsrc(a.frames + int64_t(f + 1) * a.lay.words, frame_bytes);
 #pragma unroll
             for (int k = 0; k < kStageSlots; ++k) xv[k] = buffer_load_f32(rf, voff[k], 0u);
         }
@@ -606,7 +661,7 @@ __device__ PeakSums peak_record(const ClassArgs &a, const float *__restrict__ fr
             if (!(bits[j] & kCand)) continue;
             double mu, se;
             background(a.rcoord[j], tab, a.n_bins, a.noise2, mu, se);
-            const double d = double(fr[j]) - mu;
+            const double d = double(fr[a.lay.offset(yy, xx)]) - mu;
             ps.count += 1;
             ps.I += d;
             ps.s2 += se * se;
@@ -744,7 +799,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_write(ClassArgs a) {
     __shared__ uint32_t wave_tot[kNW];
     const int tile = blockIdx.x, f = blockIdx.y;
     const int64_t p0 = (int64_t(tile) * kBlock + threadIdx.x) * PPT;
-    const float *__restrict__ fr = a.frames + int64_t(f) * a.n_pix;
+    const float *__restrict__ fr = a.frames + int64_t(f) * a.lay.words;
     const uint8_t *__restrict__ bits = a.ws.bits + int64_t(f) * a.n_pix;
     // the tile's offsets do not depend on the scan below: load them first
     const uint64_t toff = a.ws.offsets[int64_t(f) * a.tiles + tile];
@@ -769,7 +824,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_write(ClassArgs a) {
                 m &= m ? m - 1 : 0u;
             }
 #pragma unroll
-            for (int u = 0; u < kBatch; ++u) vs[u] = ks[u] >= 0 ? fr[p0 + ks[u]] : 0.0f;
+            for (int u = 0; u < kBatch; ++u) vs[u] = ks[u] >= 0 ? fr[frame_word(a.lay, p0 + ks[u])] : 0.0f;
 #pragma unroll
             for (int u = 0; u < kBatch; ++u) {
                 if (ks[u] < 0) break;
@@ -1059,6 +1114,19 @@ extern "C" size_t ss_classify_workspace(int32_t n_frames, int64_t n_pix, int32_t
     return ss::workspace_bytes(n_frames, n_pix, n_bins);
 }
 
+namespace ss {
+namespace {
+template <bool LINES, bool TILED>
+void launch_pixel_state(const StateArgs &sa, int h, dim3 grid, size_t lds, hipStream_t stream) {
+    if (h == 0) k_pixel_state<stage_slots(0), 0, LINES, TILED><<<grid, kStencilBlock, lds, stream>>>(sa);
+    else if (h == 1) k_pixel_state<stage_slots(1), 1, LINES, TILED><<<grid, kStencilBlock, lds, stream>>>(sa);
+    else if (h == 2) k_pixel_state<stage_slots(2), 2, LINES, TILED><<<grid, kStencilBlock, lds, stream>>>(sa);
+    else if (h <= 4) k_pixel_state<stage_slots(4), -1, LINES, TILED><<<grid, kStencilBlock, lds, stream>>>(sa);
+    else k_pixel_state<stage_slots(SS_MAX_PATCH / 2), -1, LINES, TILED><<<grid, kStencilBlock, lds, stream>>>(sa);
+}
+}  // namespace
+}  // namespace ss
+
 extern "C" int ss_classify(const float *frames, const uint8_t *mask, int32_t n_frames, int32_t height,
                            int32_t width, const ss_radial *radial, const ss_profile *profile,
                            const ss_params *p, uint32_t *kept_index, float *kept_value, int64_t capacity,
@@ -1071,6 +1139,9 @@ extern "C" int ss_classify(const float *frames, const uint8_t *mask, int32_t n_f
     if (n_pix >= (int64_t(1) << 29) || n_frames > 65535) return SS_ESIZE;
     if (radial->n_bins <= 0 || radial->n_bins > SS_MAX_BINS) return SS_ESIZE;
     if (p->patch < 1 || p->patch > SS_MAX_PATCH || (p->patch % 2) == 0) return SS_EINVAL;
+    Layout lay{};
+    if (n_pix > 0 && (!make_layout(height, width, radial->tile_w, radial->tile_h, lay) || lay.words >= (int64_t(1) << 29)))
+        return SS_ESIZE;
     const bool keep = kept_index || kept_value || n_kept;
     const bool pk = peaks || n_peaks;
     if (keep && (!kept_index || !kept_value || !n_kept)) return SS_EINVAL;
@@ -1091,6 +1162,7 @@ extern "C" int ss_classify(const float *frames, const uint8_t *mask, int32_t n_f
     {
         StateArgs sa;
         sa.frames = frames;
+        sa.lay = lay;
         sa.rcoord = radial->rcoord;
         sa.mask = mask;
         sa.n_frames = n_frames;
@@ -1117,25 +1189,19 @@ extern "C" int ss_classify(const float *frames, const uint8_t *mask, int32_t n_f
         if (items > (int64_t(1) << 31)) return SS_ESIZE;
         const dim3 grid(uint32_t(8 * ((items + 7) / 8)));
         // staging registers sized to the halo; patches 1, 3 and 5 unrolled;
-        // threshold lines when there is no noise level
-        if (p->noise == 0.0f) {
-            if (h == 0) k_pixel_state<stage_slots(0), 0, true><<<grid, kStencilBlock, lds, stream>>>(sa);
-            else if (h == 1) k_pixel_state<stage_slots(1), 1, true><<<grid, kStencilBlock, lds, stream>>>(sa);
-            else if (h == 2) k_pixel_state<stage_slots(2), 2, true><<<grid, kStencilBlock, lds, stream>>>(sa);
-            else if (h <= 4) k_pixel_state<stage_slots(4), -1, true><<<grid, kStencilBlock, lds, stream>>>(sa);
-            else k_pixel_state<stage_slots(SS_MAX_PATCH / 2), -1, true><<<grid, kStencilBlock, lds, stream>>>(sa);
-        } else {
-            if (h == 0) k_pixel_state<stage_slots(0), 0, false><<<grid, kStencilBlock, lds, stream>>>(sa);
-            else if (h == 1) k_pixel_state<stage_slots(1), 1, false><<<grid, kStencilBlock, lds, stream>>>(sa);
-            else if (h == 2) k_pixel_state<stage_slots(2), 2, false><<<grid, kStencilBlock, lds, stream>>>(sa);
-            else if (h <= 4) k_pixel_state<stage_slots(4), -1, false><<<grid, kStencilBlock, lds, stream>>>(sa);
-            else k_pixel_state<stage_slots(SS_MAX_PATCH / 2), -1, false><<<grid, kStencilBlock, lds, stream>>>(sa);
-        }
+        // threshold lines when there is no noise level; tile-ordered staging
+        // for tiled frame layouts
+        const bool lines = p->noise == 0.0f;
+        if (lines && lay.tiled()) launch_pixel_state<true, true>(sa, h, grid, lds, stream);
+        else if (lines) launch_pixel_state<true, false>(sa, h, grid, lds, stream);
+        else if (lay.tiled()) launch_pixel_state<false, true>(sa, h, grid, lds, stream);
+        else launch_pixel_state<false, false>(sa, h, grid, lds, stream);
         SS_RETURN_IF_LAUNCH_FAILED();
     }
 
     ClassArgs a;
     a.frames = frames;
+    a.lay = lay;
     a.n_frames = n_frames;
     a.mask = mask;
     a.rcoord = radial->rcoord;

@@ -132,6 +132,27 @@ __device__ inline int32_t buffer_load_i32(__amdgpu_buffer_rsrc_t r, uint32_t vof
     return __builtin_amdgcn_raw_buffer_load_b32(r, int(voff), int(soff), 0);
 }
 
+// Word offsets of pixels in a frame of an ss_layout: row-major (sw < 0),
+// or tiles of 2^sw x 2^sh pixels, tiles row-major, pixels row-major inside
+// a tile.
+struct Layout {
+    int32_t height, width;
+    int32_t sw, sh;   // log2 of the tile width and height; sw < 0: row-major
+    int32_t tiles_x;
+    int64_t words;    // words per frame
+
+    __host__ __device__ bool tiled() const { return sw >= 0; }
+    __host__ __device__ int64_t offset(int y, int x) const {
+        if (sw < 0) return int64_t(y) * width + x;
+        return ((int64_t(y >> sh) * tiles_x + (x >> sw)) << (sw + sh)) + ((y & ((1 << sh) - 1)) << sw) +
+               (x & ((1 << sw) - 1));
+    }
+};
+
+// The Layout of frames of height x width pixels in tiles of tile_w x tile_h
+// (0 x 0: row-major); false for a layout ss_layout_words refuses.
+bool make_layout(int32_t height, int32_t width, int32_t tile_w, int32_t tile_h, Layout &out);
+
 __global__ void k_fill_i64(int64_t *p, int64_t n, int64_t value);
 
 }  // namespace ss

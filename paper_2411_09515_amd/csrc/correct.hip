@@ -8,10 +8,28 @@
 //
 // The arithmetic is float64 and each stored value is rounded once to
 // float32: signal = f32((adc - ped) / gain), out = f32(signal / norm).
+//
+// Output frames are row-major or tiled (ss_layout).  Threads walk the
+// output in word order, 4 words (one quad of pixels in one image row) each,
+// so every store is 16 contiguous bytes of a fully written line; the raw
+// words and calibration of the quad are read at its row-major pixels.
 
 #include "common.h"
 
 namespace ss {
+
+bool make_layout(int32_t height, int32_t width, int32_t tile_w, int32_t tile_h, Layout &out) {
+    const ss_layout l{height, width, tile_w, tile_h};
+    const int64_t words = ss_layout_words(&l);
+    if (words < 0) return false;
+    out.height = height;
+    out.width = width;
+    out.words = words;
+    out.sw = tile_w == 0 ? -1 : __builtin_ctz(uint32_t(tile_w));
+    out.sh = tile_w == 0 ? -1 : __builtin_ctz(uint32_t(tile_h));
+    out.tiles_x = tile_w == 0 ? 1 : (width + tile_w - 1) / tile_w;
+    return true;
+}
 
 __global__ void k_fill_i64(int64_t *p, int64_t n, int64_t value) {
     for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
@@ -105,18 +123,60 @@ __device__ inline const uint16_t *frame_words(const RawFrames &r, int f, int64_t
 
 constexpr uint32_t kInvalidPair = 0x80008000u;  // two words with gain code 10
 
+// Raster index p of the first pixel of output quad i (words 4i .. 4i + 3,
+// pixels p .. p + 3 of one image row), or false for a quad past the image
+// edge.  Row-major: p = 4i.  Tiled (tile width >= 4): quads run through
+// a tile row by row.
+__device__ inline bool quad_site(int64_t i, const Layout &L, int64_t &p) {
+    if (!L.tiled()) {
+        p = i * 4;
+        return p < L.words;
+    }
+    const int tq = L.sw + L.sh - 2;  // log2 of the quads of a tile
+    const int64_t t = i >> tq;
+    const int q = int(i & ((int64_t(1) << tq) - 1));
+    const int64_t ty = t / L.tiles_x, tx = t - ty * L.tiles_x;
+    const int64_t y = (ty << L.sh) + (q >> (L.sw - 2));
+    const int64_t x = (tx << L.sw) + int64_t(q & ((1 << (L.sw - 2)) - 1)) * 4;
+    p = y * L.width + x;
+    return y < L.height && x < L.width;
+}
+
+// Raster index of the pixel at output word o, or false past the image edge.
+__device__ inline bool word_site(int64_t o, const Layout &L, int64_t &p) {
+    if (!L.tiled()) {
+        p = o;
+        return o < L.words;
+    }
+    const int64_t t = o >> (L.sw + L.sh);
+    const int w = int(o & ((int64_t(1) << (L.sw + L.sh)) - 1));
+    const int64_t ty = t / L.tiles_x, tx = t - ty * L.tiles_x;
+    const int64_t y = (ty << L.sh) + (w >> L.sw), x = (tx << L.sw) + (w & ((1 << L.sw) - 1));
+    p = y * L.width + x;
+    return y < L.height && x < L.width;
+}
+
 #ifndef SS_CORRECT_UNROLL
 #define SS_CORRECT_UNROLL 4
 #endif
 constexpr int kFrameUnroll = SS_CORRECT_UNROLL;
 
-// Vector path: n_pix % 4 == 0 and 8/16-byte aligned buffers.
+// Vector path: quads of pixels within image rows (row-major: n_pix % 4 ==
+// 0; tiled: width % 4 == 0) and 16-byte aligned buffers.
 __global__ __launch_bounds__(kCorrectBlock) void k_correct_vec(
-    const RawFrames raw, int n_frames, int64_t n_pix, const float *__restrict__ ped,
+    const RawFrames raw, int n_frames, const Layout L, const float *__restrict__ ped,
     const float *__restrict__ gain, const float *__restrict__ norm, float *__restrict__ out,
     int64_t *__restrict__ n_invalid) {
-    const int64_t p0 = (int64_t(blockIdx.x) * kCorrectBlock + threadIdx.x) * kVec;
-    if (p0 >= n_pix) return;
+    const int64_t qi = int64_t(blockIdx.x) * kCorrectBlock + threadIdx.x;
+    if (qi * kVec >= L.words) return;
+    const int64_t n_pix = int64_t(L.height) * L.width;
+    int64_t p0;
+    if (!quad_site(qi, L, p0)) {
+        const float nan = __builtin_nanf("");
+        for (int f = 0; f < n_frames; ++f)
+            *reinterpret_cast<float4 *>(out + int64_t(f) * L.words + qi * kVec) = make_float4(nan, nan, nan, nan);
+        return;
+    }
     PixelCal cal[kVec];
 #pragma unroll
     for (int k = 0; k < kVec; ++k) cal[k] = load_cal(ped, gain, norm, p0 + k, n_pix);
@@ -138,7 +198,7 @@ __global__ __launch_bounds__(kCorrectBlock) void k_correct_vec(
             float o[kVec];
 #pragma unroll
             for (int k = 0; k < kVec; ++k) o[k] = correct_one(words[k], cal[k], norm != nullptr, invalid);
-            *reinterpret_cast<float4 *>(out + int64_t(f) * n_pix + p0) = make_float4(o[0], o[1], o[2], o[3]);
+            *reinterpret_cast<float4 *>(out + int64_t(f) * L.words + qi * kVec) = make_float4(o[0], o[1], o[2], o[3]);
             if (invalid && n_invalid)
                 atomicAdd(reinterpret_cast<unsigned long long *>(n_invalid + f), (unsigned long long)invalid);
         }
@@ -152,11 +212,19 @@ __global__ __launch_bounds__(kCorrectBlock) void k_correct_vec(
 constexpr int kFewFrames = 2;
 
 __global__ __launch_bounds__(kCorrectBlock) void k_correct_few(
-    const RawFrames raw, int n_frames, int64_t n_pix, const float *__restrict__ ped,
+    const RawFrames raw, int n_frames, const Layout L, const float *__restrict__ ped,
     const float *__restrict__ gain, const float *__restrict__ norm, float *__restrict__ out,
     int64_t *__restrict__ n_invalid) {
-    const int64_t p0 = (int64_t(blockIdx.x) * kCorrectBlock + threadIdx.x) * kVec;
-    if (p0 >= n_pix) return;
+    const int64_t qi = int64_t(blockIdx.x) * kCorrectBlock + threadIdx.x;
+    if (qi * kVec >= L.words) return;
+    const int64_t n_pix = int64_t(L.height) * L.width;
+    int64_t p0;
+    if (!quad_site(qi, L, p0)) {
+        const float nan = __builtin_nanf("");
+        for (int f = 0; f < n_frames; ++f)
+            *reinterpret_cast<float4 *>(out + int64_t(f) * L.words + qi * kVec) = make_float4(nan, nan, nan, nan);
+        return;
+    }
     float nm[kVec];
     double rn[kVec];
 #pragma unroll
@@ -181,22 +249,29 @@ __global__ __launch_bounds__(kCorrectBlock) void k_correct_few(
             const PixelCal c{pg, pg, pg, gg, gg, gg, rg, rg, rg, nm[k], rn[k]};
             o[k] = correct_one(words[k], c, norm != nullptr, invalid);
         }
-        *reinterpret_cast<float4 *>(out + int64_t(f) * n_pix + p0) = make_float4(o[0], o[1], o[2], o[3]);
+        *reinterpret_cast<float4 *>(out + int64_t(f) * L.words + qi * kVec) = make_float4(o[0], o[1], o[2], o[3]);
         if (invalid && n_invalid)
             atomicAdd(reinterpret_cast<unsigned long long *>(n_invalid + f), (unsigned long long)invalid);
     }
 }
 
-// Scalar path for any size and alignment: one thread per pixel, all frames.
+// Scalar path for any size and alignment: one thread per output word, all
+// frames.
 __global__ __launch_bounds__(kCorrectBlock) void k_correct_scalar(
-    const RawFrames raw, int n_frames, int64_t n_pix, const float *__restrict__ ped,
+    const RawFrames raw, int n_frames, const Layout L, const float *__restrict__ ped,
     const float *__restrict__ gain, const float *__restrict__ norm, float *__restrict__ out,
     int64_t *__restrict__ n_invalid) {
-    const int64_t i = int64_t(blockIdx.x) * kCorrectBlock + threadIdx.x;
-    if (i >= n_pix) return;
+    const int64_t o = int64_t(blockIdx.x) * kCorrectBlock + threadIdx.x;
+    if (o >= L.words) return;
+    const int64_t n_pix = int64_t(L.height) * L.width;
+    int64_t i;
+    if (!word_site(o, L, i)) {
+        for (int f = 0; f < n_frames; ++f) out[int64_t(f) * L.words + o] = __builtin_nanf("");
+        return;
+    }
     const PixelCal cal = load_cal(ped, gain, norm, i, n_pix);
     for (int f = 0; f < n_frames; ++f) {
-        const int64_t at = int64_t(f) * n_pix + i;
+        const int64_t at = int64_t(f) * L.words + o;
         int invalid = 0;
         bool ok;
         const uint16_t *fr = frame_words(raw, f, n_pix, ok);
@@ -213,34 +288,53 @@ bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) ==
 
 namespace {
 
-int correct_entry(const ss::RawFrames &rf, int32_t n_frames, int64_t n_pix, const float *pedestal, const float *gain,
-                  const float *norm, float *out, int64_t *n_invalid, hipStream_t stream) {
+// Row-major frames of n_pix pixels (one row of n_pix for the indexing).
+ss::Layout raster_layout(int64_t n_pix) {
+    ss::Layout L{};
+    L.height = 1;
+    L.width = int32_t(n_pix);
+    L.sw = L.sh = -1;
+    L.tiles_x = 1;
+    L.words = n_pix;
+    return L;
+}
+
+int correct_entry(const ss::RawFrames &rf, int32_t n_frames, const ss::Layout &L, const float *pedestal,
+                  const float *gain, const float *norm, float *out, int64_t *n_invalid, hipStream_t stream) {
     using namespace ss;
-    if (n_frames < 0 || n_pix < 0 || n_pix >= (int64_t(1) << 31)) return SS_ESIZE;
     if (n_frames == 0) return SS_OK;
     if (!rf.raw || !pedestal || !gain || !out) return SS_EINVAL;
     if (n_invalid) {
         k_fill_i64<<<1, 64, 0, stream>>>(n_invalid, n_frames, 0);
         SS_RETURN_IF_LAUNCH_FAILED();
     }
+    const int64_t n_pix = int64_t(L.height) * L.width;
     if (n_pix == 0) return SS_OK;
-    const bool vec = (n_pix % kVec == 0) && aligned16(rf.raw) && aligned16(out);
+    // quads stay inside image rows: row-major needs n_pix % 4 == 0, tiled
+    // layouts width % 4 == 0 (their tiles are at least 4 wide)
+    const bool quads = L.tiled() ? (L.width % kVec == 0) : (n_pix % kVec == 0);
+    const bool vec = quads && aligned16(rf.raw) && aligned16(out);
     if (vec) {
-        const int64_t threads = n_pix / kVec;
+        const int64_t threads = L.words / kVec;
         const int64_t blocks = (threads + kCorrectBlock - 1) / kCorrectBlock;
         if (n_frames <= kFewFrames)
-            k_correct_few<<<dim3(uint32_t(blocks)), kCorrectBlock, 0, stream>>>(
-                rf, n_frames, n_pix, pedestal, gain, norm, out, n_invalid);
+            k_correct_few<<<dim3(uint32_t(blocks)), kCorrectBlock, 0, stream>>>(rf, n_frames, L, pedestal, gain,
+                                                                                norm, out, n_invalid);
         else
-            k_correct_vec<<<dim3(uint32_t(blocks)), kCorrectBlock, 0, stream>>>(
-                rf, n_frames, n_pix, pedestal, gain, norm, out, n_invalid);
+            k_correct_vec<<<dim3(uint32_t(blocks)), kCorrectBlock, 0, stream>>>(rf, n_frames, L, pedestal, gain,
+                                                                                norm, out, n_invalid);
     } else {
-        const int64_t blocks = (n_pix + kCorrectBlock - 1) / kCorrectBlock;
-        k_correct_scalar<<<dim3(uint32_t(blocks)), kCorrectBlock, 0, stream>>>(
-            rf, n_frames, n_pix, pedestal, gain, norm, out, n_invalid);
+        const int64_t blocks = (L.words + kCorrectBlock - 1) / kCorrectBlock;
+        k_correct_scalar<<<dim3(uint32_t(blocks)), kCorrectBlock, 0, stream>>>(rf, n_frames, L, pedestal, gain,
+                                                                              norm, out, n_invalid);
     }
     SS_RETURN_IF_LAUNCH_FAILED();
     return SS_OK;
+}
+
+int layout_arg(const ss_layout *layout, ss::Layout &L) {
+    if (!layout) return SS_EINVAL;
+    return ss::make_layout(layout->height, layout->width, layout->tile_w, layout->tile_h, L) ? SS_OK : SS_ESIZE;
 }
 
 }  // namespace
@@ -248,15 +342,40 @@ int correct_entry(const ss::RawFrames &rf, int32_t n_frames, int64_t n_pix, cons
 extern "C" int ss_correct(const uint16_t *raw, int32_t n_frames, int64_t n_pix, const float *pedestal,
                           const float *gain, const float *norm, float *out, int64_t *n_invalid,
                           hipStream_t stream) {
-    return correct_entry(ss::RawFrames{raw, nullptr, int64_t(n_frames)}, n_frames, n_pix, pedestal, gain, norm, out,
+    if (n_frames < 0 || n_pix < 0 || n_pix >= (int64_t(1) << 31)) return SS_ESIZE;
+    return correct_entry(ss::RawFrames{raw, nullptr, int64_t(n_frames)}, n_frames, raster_layout(n_pix), pedestal,
+                         gain, norm, out, n_invalid, stream);
+}
+
+extern "C" int ss_correct_tiled(const uint16_t *raw, int32_t n_frames, const ss_layout *layout,
+                                const float *pedestal, const float *gain, const float *norm, float *out,
+                                int64_t *n_invalid, hipStream_t stream) {
+    ss::Layout L;
+    const int rc = layout_arg(layout, L);
+    if (rc != SS_OK) return rc;
+    if (n_frames < 0) return SS_ESIZE;
+    return correct_entry(ss::RawFrames{raw, nullptr, int64_t(n_frames)}, n_frames, L, pedestal, gain, norm, out,
                          n_invalid, stream);
 }
 
 extern "C" int ss_correct_indexed(const uint16_t *ring, int64_t ring_frames, const int64_t *frame_index,
                                   int32_t n_frames, int64_t n_pix, const float *pedestal, const float *gain,
                                   const float *norm, float *out, int64_t *n_invalid, hipStream_t stream) {
-    if (ring_frames < 0) return SS_ESIZE;
+    if (ring_frames < 0 || n_frames < 0 || n_pix < 0 || n_pix >= (int64_t(1) << 31)) return SS_ESIZE;
     if (n_frames > 0 && !frame_index) return SS_EINVAL;
-    return correct_entry(ss::RawFrames{ring, frame_index, ring_frames}, n_frames, n_pix, pedestal, gain, norm, out,
+    return correct_entry(ss::RawFrames{ring, frame_index, ring_frames}, n_frames, raster_layout(n_pix), pedestal,
+                         gain, norm, out, n_invalid, stream);
+}
+
+extern "C" int ss_correct_indexed_tiled(const uint16_t *ring, int64_t ring_frames, const int64_t *frame_index,
+                                        int32_t n_frames, const ss_layout *layout, const float *pedestal,
+                                        const float *gain, const float *norm, float *out, int64_t *n_invalid,
+                                        hipStream_t stream) {
+    ss::Layout L;
+    const int rc = layout_arg(layout, L);
+    if (rc != SS_OK) return rc;
+    if (ring_frames < 0 || n_frames < 0) return SS_ESIZE;
+    if (n_frames > 0 && !frame_index) return SS_EINVAL;
+    return correct_entry(ss::RawFrames{ring, frame_index, ring_frames}, n_frames, L, pedestal, gain, norm, out,
                          n_invalid, stream);
 }

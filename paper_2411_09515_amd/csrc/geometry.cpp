@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <utility>
 #include <vector>
 
 #include "sigsep.h"
@@ -190,6 +191,78 @@ extern "C" int ss_csr_schedule(const int64_t *indptr, int32_t n_bins, int32_t *b
     for (int32_t c = SS_N_CLASSES - 1; c >= 0; --c)
         for (int32_t r = 0; r < n_bins; ++r)
             if (cls[size_t(r)] == c) bin_order[at++] = r;
+    return SS_OK;
+}
+
+namespace {
+
+bool pow2(int32_t v) { return v > 0 && (v & (v - 1)) == 0; }
+
+int64_t tiles_x_of(const ss_layout &l) { return (int64_t(l.width) + l.tile_w - 1) / l.tile_w; }
+
+// Word of pixel (y, x) in a layout (the formula of ss_layout).
+int64_t word_of(const ss_layout &l, int64_t tiles_x, int64_t y, int64_t x) {
+    if (l.tile_w == 0) return y * l.width + x;
+    return ((y / l.tile_h) * tiles_x + x / l.tile_w) * (int64_t(l.tile_w) * l.tile_h) + (y % l.tile_h) * l.tile_w +
+           x % l.tile_w;
+}
+
+}  // namespace
+
+extern "C" int64_t ss_layout_words(const ss_layout *l) {
+    if (!l) return SS_EINVAL;
+    if (l->height <= 0 || l->width <= 0) return SS_ESIZE;
+    const int64_t n = int64_t(l->height) * l->width;
+    if (n >= (int64_t(1) << 31)) return SS_ESIZE;
+    if (l->tile_w == 0 && l->tile_h == 0) return n;
+    if (!pow2(l->tile_w) || !pow2(l->tile_h) || l->tile_w < 4 || l->tile_w > 64 || l->tile_h > 64) return SS_ESIZE;
+    const int64_t ty = (int64_t(l->height) + l->tile_h - 1) / l->tile_h;
+    const int64_t words = tiles_x_of(*l) * ty * l->tile_w * l->tile_h;
+    return words >= (int64_t(1) << 31) ? SS_ESIZE : words;
+}
+
+extern "C" int ss_csr_relayout(const ss_layout *layout, int32_t n_bins, const int64_t *indptr, int32_t *indices,
+                               float *weight) {
+    if (!layout || !indptr) return SS_EINVAL;
+    const int64_t words = ss_layout_words(layout);
+    if (words < 0) return int(words);
+    if (n_bins <= 0 || n_bins > SS_MAX_BINS) return SS_ESIZE;
+    if (indptr[0] != 0) return SS_EINVAL;
+    for (int32_t r = 0; r < n_bins; ++r)
+        if (indptr[r + 1] < indptr[r]) return SS_EINVAL;
+    const int64_t nnz = indptr[n_bins];
+    if (nnz == 0) return SS_OK;
+    if (!indices || !weight) return SS_EINVAL;
+    const int64_t n_pix = int64_t(layout->height) * layout->width;
+    for (int64_t j = 0; j < nnz; ++j)
+        if (indices[j] < 0 || indices[j] >= n_pix) return SS_EINVAL;  // checked before anything is rewritten
+    const int64_t tx = layout->tile_w == 0 ? 1 : tiles_x_of(*layout);
+    std::vector<std::pair<int32_t, float>> row;
+    for (int32_t r = 0; r < n_bins; ++r) {
+        row.clear();
+        for (int64_t j = indptr[r]; j < indptr[r + 1]; ++j) {
+            const int64_t p = indices[j];
+            row.emplace_back(int32_t(word_of(*layout, tx, p / layout->width, p % layout->width)), weight[j]);
+        }
+        std::stable_sort(row.begin(), row.end(), [](const auto &a, const auto &b) { return a.first < b.first; });
+        int64_t j = indptr[r];
+        for (const auto &e : row) {
+            indices[j] = e.first;
+            weight[j] = e.second;
+            ++j;
+        }
+    }
+    return SS_OK;
+}
+
+extern "C" int ss_layout_scatter(const ss_layout *layout, const float *src, float fill, float *dst) {
+    if (!layout || !src || !dst) return SS_EINVAL;
+    const int64_t words = ss_layout_words(layout);
+    if (words < 0) return int(words);
+    for (int64_t o = 0; o < words; ++o) dst[o] = fill;
+    const int64_t tx = layout->tile_w == 0 ? 1 : tiles_x_of(*layout);
+    for (int64_t y = 0; y < layout->height; ++y)
+        for (int64_t x = 0; x < layout->width; ++x) dst[word_of(*layout, tx, y, x)] = src[y * layout->width + x];
     return SS_OK;
 }
 

@@ -80,17 +80,17 @@ class Detector:
         N, nb, B_ = self.geom.n_pix, self.geom.n_bins, self.max_batch
         ws = api.workspace_bytes(B_, N, nb)
         # frames, profile, results and their packed copies, counts
-        per = (N * 4 + nb * (4 * 8 + 3 * 4) + 2 * (self.kept_capacity * 8 + self.peak_capacity * B.PEAK_BYTES)
+        per = (self.geom.frame_words * 4 + nb * (4 * 8 + 3 * 4) + 2 * (self.kept_capacity * 8 + self.peak_capacity * B.PEAK_BYTES)
                + 32)
         return B_ * per + ws
 
 
 class _Slot:
     def __init__(self, det: Detector, device, stream, full_profile=False, n_arenas=1):
-        F, N, nb = det.max_batch, det.geom.n_pix, det.geom.n_bins
+        F, nb = det.max_batch, det.geom.n_bins
         self.det = det
         self.full_profile = full_profile
-        self.frames = torch.empty((F, N), dtype=torch.float32, device=device)
+        self.frames = torch.empty((F, det.geom.frame_words), dtype=torch.float32, device=device)
         self.n_invalid = torch.empty(F, dtype=torch.int64, device=device)
         self.profile = api.new_profile(F, nb, device)
         self.workspace = api.new_workspace(F, det.geom, device)
@@ -142,7 +142,7 @@ class _Slot:
         d = self.det
         frames = self.frames[:F]
         api.correct_indexed(d.ring, self.d_idx[:F], d.pedestal, d.gain, d.geom.norm, out=frames,
-                            n_invalid=self.n_invalid[:F])
+                            n_invalid=self.n_invalid[:F], geom=d.geom)
         prof = {k: v[:F] for k, v in self.profile.items()}
         api.sigma_clip(frames, d.geom, d.params, out=prof)
         out = {k: v[:F] for k, v in self.out.items()}

@@ -87,6 +87,27 @@ static void check_scene(const Scene &s) {
         if (s.split == SS_SPLIT_NONE) CHECK(entries[size_t(i)] == 1);
     }
 
+    // the same CSR in an 8 x 4 tiled layout: rows ascend in word offsets
+    // inside the frame, and the per-pixel norm scattered to its words
+    {
+        const ss_layout lay{s.h, s.w, 8, 4};
+        const int64_t words = ss_layout_words(&lay);
+        CHECK(words >= n);
+        std::vector<int32_t> ti(indices);
+        std::vector<float> tw(weight);
+        if (nnz > 0) CHECK(ss_csr_relayout(&lay, s.n_bins, indptr.data(), ti.data(), tw.data()) == SS_OK);
+        for (int32_t r = 0; r < s.n_bins; ++r)
+            for (int64_t j = indptr[size_t(r)]; j < indptr[size_t(r) + 1]; ++j) {
+                CHECK(ti[size_t(j)] >= 0 && ti[size_t(j)] < words);
+                if (j > indptr[size_t(r)]) CHECK(ti[size_t(j) - 1] < ti[size_t(j)]);
+            }
+        std::vector<float> dst(static_cast<size_t>(words));
+        CHECK(ss_layout_scatter(&lay, norm.data(), -1.0f, dst.data()) == SS_OK);
+        int64_t filled = 0;
+        for (float v : dst) filled += v == -1.0f ? 1 : 0;
+        CHECK(filled == words - n);
+    }
+
     // radial codes
     std::vector<uint32_t> rc(static_cast<size_t>(n));
     double c0 = 0.0, width = 0.0;
@@ -158,6 +179,12 @@ static void check_errors() {
         CHECK(rows >= 0);
         if (c >= 1 && c < SS_N_CLASSES - 1) CHECK(rows > ss_class_rows(c - 1));
     }
+    const ss_layout bad_tiles{8, 8, 3, 4};
+    CHECK(ss_layout_words(&bad_tiles) == SS_ESIZE);
+    CHECK(ss_layout_words(nullptr) == SS_EINVAL);
+    CHECK(ss_csr_relayout(nullptr, 2, bad_ptr, order, nullptr) == SS_EINVAL);
+    float one = 1.0f;
+    CHECK(ss_layout_scatter(&bad_tiles, &one, 0.0f, &one) == SS_ESIZE);
     for (int code = -5; code <= 1; ++code) CHECK(ss_strerror(code) != nullptr);
     CHECK(ss_version() > 0);
 }

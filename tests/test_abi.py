@@ -19,7 +19,7 @@ HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))
 
 def _declared():
     text = open(HEADER).read()
-    return sorted(set(re.findall(r"^(?:int|int32_t|size_t|const char \*)\s*(ss_\w+)\s*\(", text, re.M)))
+    return sorted(set(re.findall(r"^(?:int|int32_t|int64_t|size_t|const char \*)\s*(ss_\w+)\s*\(", text, re.M)))
 
 
 def test_library_exports_every_declared_symbol():
