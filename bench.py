@@ -102,10 +102,15 @@ def make_extra(workers, batched, serving):
     return uneven or None, rings or None
 
 
+# frame layout of the corrected frames: tiles of 8 x 4 pixels (one 128-byte
+# line each), or None for row-major frames (--layout rowmajor)
+TILE = (8, 4)
+
+
 def _geometry(api, torch, name, dev, cache):
     if name not in cache:
         g = synth.GEOMETRIES[name]
-        geo = api.Geometry.from_scene(g, synth.stripe_mask(g), synth.normalisation(g), dev)
+        geo = api.Geometry.from_scene(g, synth.stripe_mask(g), synth.normalisation(g), dev, tile=TILE)
         ped, gain = (torch.from_numpy(np.array(a)).to(dev) for a in synth.jungfrau_calibration(g))
         cache[name] = (geo, ped, gain)
     return cache[name]
@@ -449,7 +454,8 @@ def built_bytes(geo, n_frames, n_pix_valid, n_kept, n_peaks):
     """Bytes each C-ABI call moves once per launch as built (the corrected
     float32 frame is materialised between the stages).
 
-    correct : raw words 2 B/px/frame + corrected frame 4 B/px/frame + level-0
+    correct : raw words 2 B/px/frame + corrected frame 4 B/word/frame (a
+              tiled layout's words include its edge tiles) + level-0
               pedestal, gain and norm once (12 B/px)
     clip    : CSR index + weight once (8 B/entry) + each unmasked pixel of
               each frame once (4 B) + profile
@@ -458,7 +464,7 @@ def built_bytes(geo, n_frames, n_pix_valid, n_kept, n_peaks):
     """
     n_pix = geo.n_pix
     return dict(
-        correct=(2 + 4) * n_pix * n_frames + 12 * n_pix,
+        correct=2 * n_pix * n_frames + 4 * geo.frame_words * n_frames + 12 * n_pix,
         clip=8 * geo.nnz + 4 * n_pix_valid * n_frames + PROFILE_BYTES_PER_BIN * geo.n_bins * n_frames,
         classify=4 * n_pix * n_frames + 4 * n_pix + 8 * n_kept + 20 * n_peaks,
     )
@@ -565,9 +571,13 @@ def main():
     ap.add_argument("--inputs-cache", default="",
                     help="a .npy file holding the raw frames: read when it exists, written otherwise (several "
                          "profiler passes over the same inputs)")
+    ap.add_argument("--layout", choices=("tiles8x4", "rowmajor"), default="tiles8x4",
+                    help="layout of the corrected frames (default: tiles of 8 x 4 pixels)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 1 GiB device copy (a known-size reference for HBM counters)")
     args = ap.parse_args()
+    global TILE
+    TILE = (8, 4) if args.layout == "tiles8x4" else None
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (frames shard across GPUs "
               f"with no exchange, so the whole-job figure is N times the one-GPU value)", file=sys.stderr)
@@ -599,7 +609,7 @@ def main():
     mask = synth.stripe_mask(g)
     norm = synth.normalisation(g)
     ped, gain = synth.jungfrau_calibration(g)
-    geo = api.Geometry.from_scene(g, mask, norm, dev)
+    geo = api.Geometry.from_scene(g, mask, norm, dev, tile=TILE)
     params = api.Params(cutoff=3.0, max_iter=5, n_pick=3.0, snr=3.0, patch=3, min_count=3)
     F = args.frames
     raw = torch.from_numpy(raw_np).to(dev)
@@ -724,6 +734,7 @@ def main():
             "frames_per_step": F,
             "n_bins": geo.n_bins,
             "nnz": geo.nnz,
+            "frame_layout": "row-major" if TILE is None else f"tiles of {TILE[0]} x {TILE[1]} pixels",
         },
         "stages_ms": {k: round(v, 4) for k, v in stage.items()},
         "latency_ms_single_frame": latency,
