@@ -168,3 +168,44 @@ def test_packed_results_match_the_per_frame_layout(dev):
     # peaks only
     only = api.pack_results({k: out[k] for k in ("peaks", "n_peaks")}, 20000, 10)
     assert torch.equal(only["offsets"][6:], packed["offsets"][6:]) and int(only["offsets"][5]) == 0
+
+
+def test_tiled_detector_served_alone_batched_and_against_oracle(dev):
+    """A detector whose corrected frames are in 8 x 4 tiles (the served
+    frames go through ss_correct_indexed_tiled): each result is the same
+    alone and in batches, eager and as graph replays, and one served frame
+    matches the FP64 oracle."""
+    from parity import OracleScene
+    g = synth.JUNGFRAU1M
+    _say("setup: tiled 1m detector")
+    geo = api.Geometry.from_scene(g, synth.stripe_mask(g), synth.normalisation(g), dev, tile=(8, 4))
+    assert geo.frame_words > geo.n_pix
+    ring = np.stack([synth.uneven_frame(g, 300 + k)[0] for k in range(3)]).reshape(3, -1)
+    ped, gain = (torch.from_numpy(np.array(a)).to(dev) for a in synth.jungfrau_calibration(g))
+    p = api.Params(cutoff=3.0, max_iter=5)
+    det = serve.Detector("1m-tiled", geo, ped, gain, torch.from_numpy(ring.view(np.int16)).to(dev), p, max_batch=4)
+    server = serve.Server([det], hbm_budget=4 << 30, device=dev, full_profile=True)
+    _say("case: tiled detector, alone then batched (eager, graph replays)")
+    alone = {}
+    for k in range(3):
+        (r,), _ = server.run([serve.Request(det=0, ring_index=k, t_arrival=0.0)], realtime=False)
+        alone[k] = r
+    for mode in ("eager", "graphs"):
+        if mode == "graphs":
+            server.capture_graphs()
+        reqs = [serve.Request(det=0, ring_index=k % 3, t_arrival=0.0) for k in range(8)]
+        done, stats = server.run(reqs, realtime=False)
+        assert max(r.batch_size for r in done) >= 2, mode
+        for r in done:
+            _same(r, alone[r.ring_index], (mode, r.rid, r.ring_index, r.batch_size))
+    server.close()
+    _say("case: tiled served frame vs oracle")
+    sc = OracleScene(g)
+    r = alone[1]
+    signal, _ = sc.signal_from_raw(ring[1:2])
+    gpu = {k: getattr(r, k) for k in ("mean", "std", "sem", "sum_w", "n_members", "n_iter", "converged")}
+    res, counts = sc.check_profile(gpu, signal[0], p, "served tiled 1m")
+    c = sc.check_classify(signal[0], gpu, res, r.kept_index, r.kept_value, r.peaks, p, "served tiled 1m")
+    _say(f"  tiled 1m: bins {counts['bins']} (replayed {counts['replayed']}), kept {c['kept']}, peaks {c['peaks']}")
+    assert counts["unresolved"] == 0 and counts["replayed"] <= 1e-3 * counts["bins"] + 1
+    assert c["excused_keep"] <= 1e-3 * c["valid"] and c["excused_cand"] <= 1e-3 * c["valid"] and c["kept"] > 0
