@@ -275,3 +275,47 @@ def test_wrappers_refuse_bad_dtypes_and_shapes_before_launch():
         what="counters: shape")
     model_x = torch.zeros((5, B.SS_MLP_IN + 1))
     bad(api.Surrogate.forward, None, model_x, what="x: shape")
+
+
+def test_tiled_layout_calls_reject_bad_arguments_before_launch():
+    """The tiled correction entries and a classification naming a tiled
+    layout refuse bad layouts and pointers on the host; the torch wrappers
+    check frame shapes against a tiled geometry's frame length."""
+    import torch
+    L = B.lib()
+    fake = ctypes.c_void_p(4096)
+    ref = ctypes.byref
+    good = B.Layout(37, 52, 8, 4)
+    odd_tiles = B.Layout(37, 52, 3, 4)
+    assert L.ss_correct_tiled(fake, 1, None, fake, fake, None, fake, None, None) == B.SS_EINVAL
+    assert L.ss_correct_tiled(fake, 1, ref(odd_tiles), fake, fake, None, fake, None, None) == B.SS_ESIZE
+    assert L.ss_correct_tiled(fake, -1, ref(good), fake, fake, None, fake, None, None) == B.SS_ESIZE
+    assert L.ss_correct_tiled(None, 1, ref(good), fake, fake, None, fake, None, None) == B.SS_EINVAL
+    assert L.ss_correct_tiled(fake, 1, ref(good), fake, None, None, fake, None, None) == B.SS_EINVAL
+    assert L.ss_correct_tiled(fake, 0, ref(good), fake, fake, None, fake, None, None) == B.SS_OK
+    assert L.ss_correct_indexed_tiled(fake, 3, None, 2, ref(good), fake, fake, None, fake, None, None) == B.SS_EINVAL
+    assert L.ss_correct_indexed_tiled(fake, -1, fake, 2, ref(good), fake, fake, None, fake, None, None) == B.SS_ESIZE
+    assert L.ss_correct_indexed_tiled(fake, 3, fake, 2, ref(odd_tiles), fake, fake, None, fake, None, None) == \
+        B.SS_ESIZE
+    # classification: a radial naming tiles that ss_layout refuses
+    prof = B.Profile(*([4096] * 7))
+    p = B.Params(3.0, 5, 0, 0.0, 3.0, 0.0, 3.0, 3, 3)
+    need = L.ss_classify_workspace(2, 100, 10)
+    for tw, th in ((3, 4), (8, 3), (128, 1)):
+        rad = B.Radial(10, 0.05, 0.1, 4096, tw, th)
+        assert L.ss_classify(fake, None, 2, 10, 10, ref(rad), ref(prof), ref(p), fake, fake, 8, fake, None, 0, None,
+                             fake, need, None) == B.SS_ESIZE, (tw, th)
+
+    geo = api.Geometry(37, 53, 75e-6, 0.1, 18.3, 26.1, 17, device="cpu", tile=(8, 4))
+    assert geo.frame_words == 7 * 10 * 32 and geo.n_pix == 37 * 53
+    N = geo.n_pix
+    raw = torch.zeros((2, N), dtype=torch.uint16)
+    ped = torch.zeros((3, N), dtype=torch.float32)
+    with pytest.raises(ValueError, match="raw: expected"):
+        api.correct(raw[:, :-4].contiguous(), ped[:, :-4].contiguous(), ped[:, :-4].contiguous(), geom=geo)
+    with pytest.raises(ValueError, match="out: shape"):
+        api.correct(raw, ped, ped, out=torch.zeros((2, N), dtype=torch.float32), geom=geo)
+    with pytest.raises(ValueError, match="frames: shape"):
+        api.sigma_clip(torch.zeros((2, N), dtype=torch.float32), geo, api.Params())   # row-major frames
+    with pytest.raises(ValueError, match="tile"):
+        api.Geometry(37, 53, 75e-6, 0.1, 18.3, 26.1, 17, device="cpu", tile=(6, 4))
