@@ -1110,8 +1110,8 @@ void launch_stream(const ClipArgs &a, hipStream_t stream) {
 // SINGLE shape.  Measured on gfx950: more independent work-groups per CU
 // hide the gather latency better than more frames per work-group.
 //   class  rows     variant 0        variant 1        variant 2
-//   0      1024     256 x 4,  4 fr   128 x 8,  2 fr   256 x 4,  2 fr
-//   1      2048     256 x 8,  4 fr   128 x 16, 2 fr   256 x 8,  2 fr
+//   0      1024     128 x 8,  2 fr   256 x 4,  4 fr   256 x 4,  2 fr
+//   1      2048     128 x 16, 2 fr   256 x 8,  4 fr   256 x 8,  2 fr
 //   2      4096     256 x 16, 2 fr   128 x 32, 1 fr   256 x 16, 1 fr
 //   3      8192     256 x 32, 1 fr   512 x 16, 2 fr   1024 x 8, 4 fr
 //   4      16384    512 x 32, 1 fr   1024 x 16, 2 fr  512 x 32, 2 fr
@@ -1161,11 +1161,11 @@ void launch_class(const ClipArgs &a, int c, int variant, int mode, hipStream_t s
     }
     if (mode != MODE_CLIP || variant < 0 || variant > 2) variant = 0;
     switch (c * 3 + variant) {
-        case 0: launch_shape<1024, 256, 4, 4, 4>(a, mode, stream); break;
-        case 1: launch_plain<1024, 128, 8, 2, 4>(a, stream); break;
+        case 0: launch_shape<1024, 128, 8, 2, 4>(a, mode, stream); break;
+        case 1: launch_plain<1024, 256, 4, 4, 4>(a, stream); break;
         case 2: launch_plain<1024, 256, 4, 2, 4>(a, stream); break;
-        case 3: launch_shape<2048, 256, 8, 4, 4>(a, mode, stream); break;
-        case 4: launch_plain<2048, 128, 16, 2, 4>(a, stream); break;
+        case 3: launch_shape<2048, 128, 16, 2, 4>(a, mode, stream); break;
+        case 4: launch_plain<2048, 256, 8, 4, 4>(a, stream); break;
         case 5: launch_plain<2048, 256, 8, 2, 4>(a, stream); break;
         case 6: launch_shape<4096, 256, 16, 2, 4>(a, mode, stream); break;
         case 7: launch_plain<4096, 128, 32, 1, 4>(a, stream); break;
@@ -1202,11 +1202,11 @@ void launch_class_multi(MultiArgs &m, int c, int variant, hipStream_t stream) {
         return;
     }
     switch (c * 3 + variant) {
-        case 0: launch_multi<1024, 256, 4, 4, 4>(m, stream); break;
-        case 1: launch_multi<1024, 128, 8, 2, 4>(m, stream); break;
+        case 0: launch_multi<1024, 128, 8, 2, 4>(m, stream); break;
+        case 1: launch_multi<1024, 256, 4, 4, 4>(m, stream); break;
         case 2: launch_multi<1024, 256, 4, 2, 4>(m, stream); break;
-        case 3: launch_multi<2048, 256, 8, 4, 4>(m, stream); break;
-        case 4: launch_multi<2048, 128, 16, 2, 4>(m, stream); break;
+        case 3: launch_multi<2048, 128, 16, 2, 4>(m, stream); break;
+        case 4: launch_multi<2048, 256, 8, 4, 4>(m, stream); break;
         case 5: launch_multi<2048, 256, 8, 2, 4>(m, stream); break;
         case 6: launch_multi<4096, 256, 16, 2, 4>(m, stream); break;
         case 7: launch_multi<4096, 128, 32, 1, 4>(m, stream); break;
