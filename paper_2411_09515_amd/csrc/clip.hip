@@ -772,13 +772,28 @@ __device__ __forceinline__ void clip_body(const ClipArgs &a, int g, int bin) {
 
     // rejection passes
     for (int k = 0;; ++k) {
+        // One frame per group (the plain clip): this pass's bounds and flags
+        // are read together once, one LDS round trip at the head of the
+        // pass instead of a read of the flag, a branch, then a read of the
+        // bounds (with more frames the held copies would cost registers).
+        constexpr bool HOLD = FB == 1 && !SUR && !SKETCH;
+        ClipBounds bnd_f[FB];
+        int go_f[FB], refresh_f[FB];
+#pragma unroll
+        for (int f = 0; f < FB; ++f) {
+            bnd_f[f] = ctl[f].bounds;
+            go_f[f] = ctl[f].go;
+            refresh_f[f] = ctl[f].refresh;
+        }
+        auto go_of = [&](int f) { return HOLD ? go_f[f] : ctl[f].go; };
+        auto bnd_of = [&](int f) { return HOLD ? bnd_f[f] : ctl[f].bounds; };
         bool any = false;
 #pragma unroll
-        for (int f = 0; f < FB; ++f) any = any || ctl[f].go != 0;
+        for (int f = 0; f < FB; ++f) any = any || go_of(f) != 0;
         if (!any) break;
 #pragma unroll
         for (int f = 0; f < FB; ++f) {
-            if (!(ctl[f].go && ctl[f].refresh)) continue;
+            if (!(go_of(f) && (HOLD ? refresh_f[f] : ctl[f].refresh))) continue;
             // re-accumulate the surviving members around the current mean
             const double Kn = ctl[f].mean;
             double t[NSUM] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
@@ -797,6 +812,8 @@ __device__ __forceinline__ void clip_body(const ClipArgs &a, int g, int bin) {
                 ctl[f] = c;
             }
             __syncthreads();
+            bnd_f[f] = ctl[f].bounds;
+            go_f[f] = ctl[f].go;
         }
         // running sums of the removed members of the frames this wave
         // finishes (frames wid, wid + NW, ...), over the rounds of the pass
@@ -813,8 +830,8 @@ __device__ __forceinline__ void clip_body(const ClipArgs &a, int g, int bin) {
 #pragma unroll
             for (int f = 0; f < FB; ++f) {
                 int used = 0;
-                if (ctl[f].go) {
-                    const ClipBounds bnd = ctl[f].bounds;
+                if (go_of(f)) {
+                    const ClipBounds bnd = bnd_of(f);
 #pragma unroll
                     for (int e = 0; e < EPT; ++e) {
                         const bool out = !(SUR && ((gone[f] >> e) & 1u)) && clipped(SS_V(f, e), bnd);
@@ -850,7 +867,7 @@ __device__ __forceinline__ void clip_body(const ClipArgs &a, int g, int bin) {
 #pragma unroll
             for (int j = 0; j < FPW; ++j) {
                 const int f = wid + j * NW;
-                if (f >= FB || !ctl[f].go) continue;
+                if (f >= FB || !go_of(f)) continue;
                 const double Kc = ctl[f].K;
                 // kListGroup lists at a time: their counts and this lane's
                 // entries are read together (one LDS round trip), then added
