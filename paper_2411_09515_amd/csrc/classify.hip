@@ -246,10 +246,9 @@ __device__ inline int64_t frame_word(const Layout &L, int64_t p) {
     return L.offset(int(y), int(uint32_t(p) - y * uint32_t(L.width)));
 }
 
-__device__ inline void background(uint32_t rc, const Seg *__restrict__ tab, int n_bins, double noise2,
-                                  double &mu, double &se) {
-    const int t1 = min(int(rc >> SS_RC_FRAC_BITS), n_bins);
-    const double frac = double(rc & ((1u << SS_RC_FRAC_BITS) - 1u)) * (1.0 / double(1u << SS_RC_FRAC_BITS));
+// Background (mu, sigma_eff) at fraction frac of centre interval t1.
+__device__ inline void background_at(int t1, double frac, const Seg *__restrict__ tab, double noise2, double &mu,
+                                     double &se) {
     const Seg s = tab[t1];
     const double u = (double(t1 - 1 - s.lo) + frac) * s.inv_span;
     mu = s.m_lo + s.dm * u;
@@ -257,14 +256,23 @@ __device__ inline void background(uint32_t rc, const Seg *__restrict__ tab, int 
     se = sqrt(sd * sd + noise2);
 }
 
+__device__ inline void background(uint32_t rc, const Seg *__restrict__ tab, int n_bins, double noise2,
+                                  double &mu, double &se) {
+    const int t1 = min(int(rc >> SS_RC_FRAC_BITS), n_bins);
+    const double frac = double(rc & ((1u << SS_RC_FRAC_BITS) - 1u)) * (1.0 / double(1u << SS_RC_FRAC_BITS));
+    background_at(t1, frac, tab, noise2, mu, se);
+}
+
 
 // ---- per-pixel state and peak test ---------------------------------------------------
 
-__device__ inline uint8_t pixel_bits(float x, uint32_t rc, bool masked, const Seg *__restrict__ tab, int n_bins,
-                                     double noise2, double n_pick, double snr) {
-    if (rc == SS_RC_MASKED || masked || !isfinite(x)) return 0;
+// State bits of an unmasked pixel of value x at fraction frac of centre
+// interval t1, in float64.
+__device__ inline uint8_t pixel_bits(float x, int t1, double frac, const Seg *__restrict__ tab, double noise2,
+                                     double n_pick, double snr) {
+    if (!isfinite(x)) return 0;
     double mu, se;
-    background(rc, tab, n_bins, noise2, mu, se);
+    background_at(t1, frac, tab, noise2, mu, se);
     const double d = double(x) - mu;
     return kValid | (d > n_pick * se ? kKeep : 0) | (d >= snr * se ? kCand : 0);
 }
@@ -307,6 +315,23 @@ __device__ inline uint8_t pixel_bits_lines(float x, float frac, const SegF &tl, 
     return uint8_t(valid ? (near ? uint32_t(kUndecided) : bits) : 0u);
 }
 
+// pixel_bits_lines when n_pick == snr: the two lines are the same (same
+// float64 expression), and a value further than tol from it is either above
+// both thresholds or at most both, so one fma and one compare decide keep
+// and candidate together.
+__device__ inline uint8_t pixel_bits_line(float x, float frac, float ta, float tb, float tol) {
+    const bool valid = frac == frac && __builtin_isfinite(x);
+    const float t = fmaf(tb, frac, ta);
+    const bool near = fabsf(x - t) <= tol;
+    const uint32_t bits = x > t ? uint32_t(kValid | kKeep | kCand) : uint32_t(kValid);
+    return uint8_t(valid ? (near ? uint32_t(kUndecided) : bits) : 0u);
+}
+
+// How k_pixel_state decides keep and candidate: from the background lines
+// (with a noise level), from the two threshold lines, or from one line
+// when n_pick == snr.
+enum StateMode { kModeBackground = 0, kModeLines = 1, kModeLine = 2 };
+
 // 2-D stencil tile (core pixels), work-group size and frames per
 // work-group; compile-time tunables.
 #ifndef SS_STENCIL_TILE_H
@@ -327,6 +352,25 @@ constexpr int kStencilBlock = SS_STENCIL_BLOCK;
 constexpr int kFramesPerBlock = SS_STENCIL_FRAMES;
 // staged pixels per thread for a halo of h pixels
 constexpr int stage_slots(int h) { return ((kTileH + 2 * h) * (kTileW + 2 * h) + kStencilBlock - 1) / kStencilBlock; }
+// staging slots of the kernel that runs half width h (patches 1, 3 and 5
+// have their own, 7 and 9 share one, wider ones another)
+constexpr int state_slots(int h) {
+    return h <= 2 ? stage_slots(h) : h <= 4 ? stage_slots(4) : stage_slots(SS_MAX_PATCH / 2);
+}
+// LDS of k_pixel_state for a staged region of rn pixels: the region's radial
+// codes during set-up, whose bytes then hold two buffers of per-wave
+// candidate lists (a wave lists at most all of its staged slots), then two
+// buffers of staged values and two of pixel-state bytes, each with room for
+// every slot (padding slots store past the region, where nothing reads).
+constexpr int kStateWaves = kStencilBlock / kWave;
+constexpr size_t state_list_cap(int slots) { return size_t(slots) * kWave; }
+constexpr size_t state_head_bytes(int rn, int slots) {
+    const size_t rc = size_t(rn) * 4, lists = 2 * kStateWaves * state_list_cap(slots) * sizeof(uint16_t);
+    return ((rc > lists ? rc : lists) + 15) & ~size_t(15);
+}
+constexpr size_t state_lds_bytes(int rn, int slots) {
+    return state_head_bytes(rn, slots) + size_t(slots) * kStencilBlock * 10;
+}
 
 struct StateArgs {
     const float *frames;  // [n_frames][lay.words], in layout lay
@@ -388,7 +432,7 @@ __device__ inline bool patch_is_peak(const float *v_s, const uint8_t *b_s, int e
                 const bool before = dy < KH || (dy == KH && dx < KH);
                 const bool valid = (bq & kValid) != 0;
                 if (!centre) best = best & !(valid & (before ? vq >= vi : vq > vi));
-                count += (bq & (kValid | kCand)) == (kValid | kCand) ? 1 : 0;
+                count += int((bq >> 2) & 1u);  // kCand (a candidate is valid)
             }
         return best & (count >= min_count);
     }
@@ -419,6 +463,15 @@ __device__ inline bool patch_is_peak(const float *v_s, const uint8_t *b_s, int e
 // the region into row groups of whole rows (the first and last may be
 // partial) and each row group into blocks of whole columns; a row group is
 // stored block after block, each block row-major.
+// floor(n / d) for 0 <= n < 2^13 and 1 <= d <= 64: (n + 1/2) / d lies at
+// least 1/(2d) >= 2^-7 from an integer, and the float32 product with the
+// hardware reciprocal (within 1 ulp) is within 2^13 * 2^-22 = 2^-9 of it.
+__device__ inline int small_div(int n, int d) {
+    return int((float(n) + 0.5f) * __builtin_amdgcn_rcpf(float(d)));
+}
+
+// (Row groups and blocks are at most 64 pixels on a side, the region at
+// most 78 wide, so the positions divided below stay under 2^13.)
 __device__ inline int tile_order_slot(int s, int RW, int RH, int Y0, int X0, int sw, int sh, uint32_t magic) {
     const int oy = Y0 & ((1 << sh) - 1), ox = X0 & ((1 << sw) - 1);
     const int r = int((uint32_t(s) * magic) >> 20);       // region row of s in row-major order
@@ -426,23 +479,30 @@ __device__ inline int tile_order_slot(int s, int RW, int RH, int Y0, int X0, int
     const int r0 = max(0, (gi << sh) - oy), r1 = min(RH, ((gi + 1) << sh) - oy);
     const int gh = r1 - r0;
     const int w = s - r0 * RW;                              // position in the row group
-    const int gj = (w / gh + ox) >> sw;                     // block of the row group
+    const int gj = (small_div(w, gh) + ox) >> sw;           // block of the row group
     const int c0 = max(0, (gj << sw) - ox), c1 = min(RW, ((gj + 1) << sw) - ox);
     const int u = w - c0 * gh;
     const int gw = c1 - c0;
-    return (r0 + u / gw) * RW + c0 + u % gw;
+    const int q = small_div(u, gw);
+    return (r0 + q) * RW + c0 + (u - q * gw);
 }
 
-template <int kStageSlots, int kH, bool LINES, bool TILED>
-__global__ __launch_bounds__(kStencilBlock) __attribute__((amdgpu_waves_per_eu(kH == 0 || kH == 1 ? 8 : 1)))
+template <int kStageSlots, int kH, int MODE, bool TILED>
+__global__ __launch_bounds__(kStencilBlock) __attribute__((amdgpu_waves_per_eu(kH == 0 || kH == 1 ? 8 : kStageSlots <= 7 ? 5 : 4)))
 void k_pixel_state(StateArgs a) {
     extern __shared__ unsigned char lds[];
-    const int h = a.half;
+    // region sizes are compile-time for the unrolled patches, so that the
+    // LDS buffers of a frame sit at constant offsets
+    const int h = kH >= 0 ? kH : a.half;
     const int RW = kTileW + 2 * h, RH = kTileH + 2 * h, RN = RW * RH;
-    // radial codes once; values and pixel bits double-buffered by frame
-    uint32_t *rc_s = reinterpret_cast<uint32_t *>(lds);
-    float *v_base = reinterpret_cast<float *>(lds + size_t(RN) * 4);
-    uint8_t *b_base = lds + size_t(RN) * 12;
+    constexpr int SN = kStageSlots * kStencilBlock;  // buffer length: every slot
+    const size_t head = state_head_bytes(RN, kStageSlots);
+    uint32_t *rc_s = reinterpret_cast<uint32_t *>(lds);    // set-up only
+    uint16_t *lists = reinterpret_cast<uint16_t *>(lds);   // same bytes, afterwards
+    float *v_base = reinterpret_cast<float *>(lds + head);
+    uint8_t *b_base = lds + head + size_t(SN) * 8;
+    constexpr int kCap = int(state_list_cap(kStageSlots));
+    __shared__ uint32_t cnt_s[2][kStateWaves];
 
     // Work-groups go to the 8 XCDs round robin; work-group g takes item
     // (g % 8) * per + g / 8 of the row-major list (frame group, tile row,
@@ -463,10 +523,8 @@ void k_pixel_state(StateArgs a) {
     const int f1 = min(a.n_frames, f0 + kFramesPerBlock);
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
-    // per wave: LDS indices of its candidate core pixels (one frame at a time)
+    const int wave = __builtin_amdgcn_readfirstlane(tid) / kWave;
     constexpr int kCore = kTileH * kTileW / kStencilBlock;
-    __shared__ uint16_t list_s[kStencilBlock / kWave][kCore * kWave];
-    uint16_t *list = list_s[tid / kWave];
     // e / RW as (e * magic) >> 20, exact for e < 2^20 / RW (RN is far smaller)
     const uint32_t magic = ((1u << 20) + uint32_t(RW) - 1u) / uint32_t(RW);
 
@@ -483,14 +541,18 @@ void k_pixel_state(StateArgs a) {
     }
     __syncthreads();
     // Per staged slot, fixed over the frames: the pixel's byte offset in a
-    // frame (clamped into the frame; out-of-frame and padding slots are
-    // masked), its interval's byte offset in a frame's float32 table, and
-    // its fraction of the interval (NaN when masked).  Frames hold fewer
-    // than 2^29 pixels, so byte offsets fit 32 bits.
+    // frame (beyond the frame for masked, out-of-frame and padding slots,
+    // whose loads then read 0), its interval's byte offset in a frame's
+    // float32 table, and its fraction of the interval (NaN when masked).
+    // Frames hold fewer than 2^29 words, so byte offsets fit 32 bits.
     // With a tiled frame layout, slot k of a thread is region pixel e_k
     // (tile by tile), kept in the high half of toff[k] (table offsets are
     // below 2^16 bytes, region indices too); otherwise region pixel
-    // tid + k * kStencilBlock.
+    // tid + k * kStencilBlock.  Table offsets are multiples of 16: bit 2
+    // (kCand) of toff[k] marks the tile's own (core) pixels, not halo, so
+    // that bv & toff is kCand exactly for the core candidates.
+    static_assert(sizeof(SegF) == 16 && kCand == 4, "a flag bit below the table offsets");
+    const uint32_t frame_bytes = uint32_t(a.lay.words) * 4u;
     uint32_t voff[kStageSlots], toff[kStageSlots];
     float frac[kStageSlots];
 #pragma unroll
@@ -500,18 +562,20 @@ void k_pixel_state(StateArgs a) {
         if constexpr (TILED)
             e = sk < RN ? tile_order_slot(sk, RW, RH, ty0 - h, tx0 - h, a.lay.sw, a.lay.sh, magic) : RN;
         const int ec = min(e, RN - 1);
-        const int r = int((uint32_t(ec) * magic) >> 20);
+        const int r = int((uint32_t(ec) * magic) >> 20), c = ec - r * RW;
         const int y = min(max(ty0 - h + r, 0), a.height - 1);
-        const int x = min(max(tx0 - h + (ec - r * RW), 0), a.width - 1);
-        voff[k] = uint32_t(a.lay.offset(y, x)) * 4u;
+        const int x = min(max(tx0 - h + c, 0), a.width - 1);
         const uint32_t rc = e < RN ? rc_s[e] : SS_RC_MASKED;
+        voff[k] = rc == SS_RC_MASKED ? frame_bytes : uint32_t(a.lay.offset(y, x)) * 4u;
         toff[k] = uint32_t(min(int(rc >> SS_RC_FRAC_BITS), a.n_bins)) * uint32_t(sizeof(SegF));
         if constexpr (TILED) toff[k] |= uint32_t(e) << 16;
         frac[k] = rc == SS_RC_MASKED ? __builtin_nanf("")
                                      : float(rc & ((1u << SS_RC_FRAC_BITS) - 1u)) * (1.0f / float(1u << SS_RC_FRAC_BITS));
+        const bool core = e < RN && r >= h && r < h + kTileH && c >= h && c < h + kTileW;
+        if (core) toff[k] |= kCand;
     }
-    // the tile's core pixels this thread tests and writes: LDS index and
-    // offset in a frame (kNoPixel outside the frame)
+    // the tile's core pixels this thread stores: LDS index and offset in a
+    // frame (kNoPixel outside the frame)
     static_assert(kTileH * kTileW % kStencilBlock == 0, "whole core pixels per thread");
     constexpr uint32_t kNoPixel = 0xFFFFFFFFu;
     uint32_t soff[kCore];
@@ -524,52 +588,78 @@ void k_pixel_state(StateArgs a) {
         soff[j] = (y < a.height && x < a.width) ? uint32_t(y) * uint32_t(a.width) + uint32_t(x) : kNoPixel;
         cidx[j] = (ly + h) * RW + (lx + h);
     }
+    __syncthreads();  // the radial codes are dead; their bytes hold the lists
+    // Only the last slot can lie wholly past the region for a wave (every
+    // earlier slot index is below RN); such a wave skips it (its loads would
+    // read 0, its pixels are masked).
+    const bool last_live = wave * kWave + (kStageSlots - 1) * kStencilBlock < RN;
+#define SS_SLOT_LIVE(k) ((k) < kStageSlots - 1 || last_live)
 
-    // Frame f's values are loaded while frame f - 1 is classified and its
-    // patches tested (one frame ahead), and the two LDS buffers alternate,
-    // so one barrier per frame separates staging from the patch test: a
-    // thread stages frame f + 1 only after the barrier of frame f, which
-    // every thread reaches after its patch tests of frame f - 1.
-    const uint32_t frame_bytes = uint32_t(a.lay.words) * 4u;
     const uint32_t table_bytes = uint32_t(a.n_bins + 1) * uint32_t(sizeof(SegF));
     float xv[kStageSlots];
     if (f0 < f1) {
         const __amdgpu_buffer_rsrc_t rf = buffer_rsrc(a.frames + int64_t(f0) * a.lay.words, frame_bytes);
 #pragma unroll
-        for (int k = 0; k < kStageSlots; ++k) xv[k] = buffer_load_f32(rf, voff[k], 0u);
+        for (int k = 0; k < kStageSlots; ++k) xv[k] = SS_SLOT_LIVE(k) ? buffer_load_f32(rf, voff[k], 0u) : 0.0f;
     }
+    // Frame f's values are loaded while frame f - 1 is classified (one frame
+    // ahead) and the LDS buffers alternate by frame, so one barrier per frame
+    // separates staging from the patch tests: buffer P is staged again two
+    // frames later, after a barrier that every wave reaches only once it is
+    // done with the frame before.  Each wave lists the candidates among its
+    // staged core pixels before the barrier; after it, the work-group's
+    // candidates take the patch test 64 per wave (batches rotated over the
+    // waves by frame, so one wave tests a tile's usual few dozen), each
+    // tester stores its candidate's state byte, and the owners of the other
+    // core pixels store theirs: every byte is written once.
     for (int f = f0; f < f1; ++f) {
-        float *v_s = v_base + ((f - f0) & 1) * RN;
-        uint8_t *b_s = b_base + ((f - f0) & 1) * RN;
+        const int P = (f - f0) & 1;
+        float *v_s = v_base + P * SN;
+        uint8_t *b_s = b_base + P * SN;
+        // redefined per frame, so the slot words below are masked and
+        // shifted here, not held masked and shifted across frames
+        uint32_t tmask = 0xFFF0u, hi = 16u;
+        asm volatile("" : "+s"(tmask), "+s"(hi));
         uint8_t bv[kStageSlots];
         {
-            const SegF *tbl = LINES ? a.ws.tablet : a.ws.tablef;
+            const SegF *tbl = MODE == kModeBackground ? a.ws.tablef : a.ws.tablet;
             const __amdgpu_buffer_rsrc_t rt = buffer_rsrc(tbl + int64_t(f) * (a.n_bins + 1), table_bytes);
             SegF sg[kStageSlots];
 #pragma unroll
             for (int k = 0; k < kStageSlots; ++k) {
                 // (element access on the builtin's vector result is not used:
-                // copying the whole vector out keeps the 16-byte load intact)
-                uint32_t to = toff[k];
-                if constexpr (TILED) {
-                    asm volatile("" : "+v"(to));  // masked here, not held masked across frames
-                    to &= 0xFFFFu;
+                // copying the whole vector out keeps the load intact); one
+                // line is the entry's first 8 bytes
+                sg[k] = SegF{0.0f, 0.0f, 0.0f, 0.0f};
+                if (!SS_SLOT_LIVE(k)) continue;
+                const uint32_t to = toff[k] & tmask;
+                if constexpr (MODE == kModeLine) {
+                    const auto q = __builtin_amdgcn_raw_buffer_load_b64(rt, int(to), 0, 0);
+                    __builtin_memcpy(&sg[k], &q, 8);
+                } else {
+                    const auto q = __builtin_amdgcn_raw_buffer_load_b128(rt, int(to), 0, 0);
+                    __builtin_memcpy(&sg[k], &q, sizeof(SegF));
                 }
-                const auto q = __builtin_amdgcn_raw_buffer_load_b128(rt, int(to), 0, 0);
-                __builtin_memcpy(&sg[k], &q, sizeof(SegF));
             }
-            if constexpr (LINES) {
+            if constexpr (MODE == kModeLine) {
                 const float tol = a.ws.tolf[f];
 #pragma unroll
-                for (int k = 0; k < kStageSlots; ++k) bv[k] = pixel_bits_lines(xv[k], frac[k], sg[k], tol);
+                for (int k = 0; k < kStageSlots; ++k)
+                    bv[k] = SS_SLOT_LIVE(k) ? pixel_bits_line(xv[k], frac[k], sg[k].a, sg[k].b, tol) : 0;
+            } else if constexpr (MODE == kModeLines) {
+                const float tol = a.ws.tolf[f];
+#pragma unroll
+                for (int k = 0; k < kStageSlots; ++k)
+                    bv[k] = SS_SLOT_LIVE(k) ? pixel_bits_lines(xv[k], frac[k], sg[k], tol) : 0;
             } else {
 #pragma unroll
                 for (int k = 0; k < kStageSlots; ++k)
-                    bv[k] = pixel_bits_fast(xv[k], frac[k], sg[k], a.noise2f, a.n_pick_f, a.snr_f);
+                    bv[k] = SS_SLOT_LIVE(k) ? pixel_bits_fast(xv[k], frac[k], sg[k], a.noise2f, a.n_pick_f, a.snr_f) : 0;
             }
         }
         // pixels within rounding of a threshold, in float64 (rare; the
-        // float32 table entries are no longer live here)
+        // float32 table entries are no longer live here; the fraction is
+        // exact in float32, the interval is the table offset's)
         bool undecided = false;
 #pragma unroll
         for (int k = 0; k < kStageSlots; ++k) undecided = undecided || bv[k] == kUndecided;
@@ -578,65 +668,68 @@ void k_pixel_state(StateArgs a) {
 #pragma unroll
             for (int k = 0; k < kStageSlots; ++k)
                 if (bv[k] == kUndecided)
-                    bv[k] = pixel_bits(xv[k], rc_s[TILED ? int(toff[k] >> 16) : tid + k * kStencilBlock], false, tab,
-                                       a.n_bins, a.noise2, a.n_pick,
-                                       a.snr);
+                    bv[k] = pixel_bits(xv[k], int((toff[k] & 0xFFF0u) / uint32_t(sizeof(SegF))), double(frac[k]),
+                                       tab, a.noise2, a.n_pick, a.snr);
         }
+        uint16_t *own = lists + (P * kStateWaves + wave) * kCap;
+        uint32_t n = 0;
 #pragma unroll
         for (int k = 0; k < kStageSlots; ++k) {
-            const int sk = tid + k * kStencilBlock;
-            int e = sk;
-            if constexpr (TILED) {
-                // formed here each frame: kept out of the loop, the LDS
-                // addresses of every slot would hold registers of their own
-                uint32_t t = toff[k];
-                asm volatile("" : "+v"(t));
-                e = int(t >> 16);
-            }
-            if (k < kStageSlots - 1 || sk < RN) {
-                v_s[e] = frac[k] == frac[k] ? xv[k] : 0.0f;
-                b_s[e] = bv[k];
-            }
+            if (!SS_SLOT_LIVE(k)) continue;
+            const int e = TILED ? int(toff[k] >> hi) : tid + k * kStencilBlock;
+            v_s[e] = xv[k];
+            b_s[e] = bv[k];
+            const bool cand = (uint32_t(bv[k]) & toff[k]) != 0;
+            const uint64_t m = __builtin_amdgcn_ballot_w64(cand);
+            if (cand)
+                own[__builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), n))] =
+                    uint16_t(e);
+            n += uint32_t(__popcll(m));
         }
+        if (lane == 0) cnt_s[P][wave] = uint32_t(n);
         if (f + 1 < f1) {
             const __amdgpu_buffer_rsrc_t rf = buffer_rsrc(a.frames + int64_t(f + 1) * a.lay.words, frame_bytes);
 #pragma unroll
-            for (int k = 0; k < kStageSlots; ++k) xv[k] = buffer_load_f32(rf, voff[k], 0u);
+            for (int k = 0; k < kStageSlots; ++k)
+                if (SS_SLOT_LIVE(k)) xv[k] = buffer_load_f32(rf, voff[k], 0u);
         }
         __syncthreads();
-        // The wave's candidates (of all its core slots) are listed in LDS and
-        // take the patch test 64 at a time: a slot where one lane holds a
-        // candidate no longer costs the whole wave a test.  A lane that finds
-        // a peak sets kPeak in the pixel's LDS byte (the patch tests read
-        // only kValid and kCand of their neighbours), and the owners read
-        // their bytes back before the store.
-        uint8_t bj[kCore];
-        int n_list = 0;
-#pragma unroll
-        for (int j = 0; j < kCore; ++j) {
-            bj[j] = b_s[cidx[j]];
-            const bool cand = (bj[j] & kCand) != 0;
-            const uint64_t m = __builtin_amdgcn_ballot_w64(cand);
-            if (cand) list[n_list + lanes_below(m)] = uint16_t(cidx[j]);
-            n_list += __popcll(m);
-        }
-        if (n_list > 0) {
-            __builtin_amdgcn_wave_barrier();
-            for (int base = 0; base < n_list; base += kWave) {
-                if (base + lane < n_list) {
-                    const int e = list[base + lane];
-                    if (patch_is_peak<kH>(v_s, b_s, e, RW, h, a.min_count)) b_s[e] = uint8_t(b_s[e] | kPeak);
-                }
-            }
-            __builtin_amdgcn_wave_barrier();
-#pragma unroll
-            for (int j = 0; j < kCore; ++j) bj[j] = b_s[cidx[j]];
-        }
         const __amdgpu_buffer_rsrc_t rb = buffer_rsrc(a.ws.bits + int64_t(f) * a.n_pix, uint32_t(a.n_pix));
 #pragma unroll
-        for (int j = 0; j < kCore; ++j)
-            if (soff[j] != kNoPixel) __builtin_amdgcn_raw_buffer_store_b8(bj[j], rb, int(soff[j]), 0, 0);
+        for (int j = 0; j < kCore; ++j) {
+            const uint8_t b = b_s[cidx[j]];
+            if (soff[j] != kNoPixel && (b & kCand) == 0) __builtin_amdgcn_raw_buffer_store_b8(b, rb, int(soff[j]), 0, 0);
+        }
+        // candidate i of the work-group is entry i - p_w of wave w's list,
+        // p_w the candidates of the waves before w: list slot
+        // i + sum over w' < w of (kCap - c_w')
+        static_assert((kStateWaves & (kStateWaves - 1)) == 0, "waves per work-group a power of two");
+        int cw[kStateWaves], total = 0;
+#pragma unroll
+        for (int w = 0; w < kStateWaves; ++w) {
+            cw[w] = __builtin_amdgcn_readfirstlane(int(cnt_s[P][w]));
+            total += cw[w];
+        }
+        const uint16_t *lists_p = lists + P * kStateWaves * kCap;
+        for (int b = (wave - (f - f0)) & (kStateWaves - 1); b * kWave < total; b += kStateWaves) {
+            const int i = b * kWave + lane;
+            if (i < total) {
+                int slot = i, before = 0;
+#pragma unroll
+                for (int w = 0; w + 1 < kStateWaves; ++w) {
+                    before += cw[w];
+                    slot += i >= before ? kCap - cw[w] : 0;
+                }
+                const int e = lists_p[slot];
+                const bool peak = patch_is_peak<kH>(v_s, b_s, e, RW, h, a.min_count);
+                const int r = int((uint32_t(e) * magic) >> 20);
+                const uint32_t y = uint32_t(ty0 - h + r), x = uint32_t(tx0 - h + (e - r * RW));
+                __builtin_amdgcn_raw_buffer_store_b8(uint8_t(b_s[e] | (peak ? kPeak : 0)), rb,
+                                                     int(y * uint32_t(a.width) + x), 0, 0);
+            }
+        }
     }
+#undef SS_SLOT_LIVE
 }
 
 // ---- peak test and record ------------------------------------------------------------
@@ -1116,13 +1209,13 @@ extern "C" size_t ss_classify_workspace(int32_t n_frames, int64_t n_pix, int32_t
 
 namespace ss {
 namespace {
-template <bool LINES, bool TILED>
+template <int MODE, bool TILED>
 void launch_pixel_state(const StateArgs &sa, int h, dim3 grid, size_t lds, hipStream_t stream) {
-    if (h == 0) k_pixel_state<stage_slots(0), 0, LINES, TILED><<<grid, kStencilBlock, lds, stream>>>(sa);
-    else if (h == 1) k_pixel_state<stage_slots(1), 1, LINES, TILED><<<grid, kStencilBlock, lds, stream>>>(sa);
-    else if (h == 2) k_pixel_state<stage_slots(2), 2, LINES, TILED><<<grid, kStencilBlock, lds, stream>>>(sa);
-    else if (h <= 4) k_pixel_state<stage_slots(4), -1, LINES, TILED><<<grid, kStencilBlock, lds, stream>>>(sa);
-    else k_pixel_state<stage_slots(SS_MAX_PATCH / 2), -1, LINES, TILED><<<grid, kStencilBlock, lds, stream>>>(sa);
+    if (h == 0) k_pixel_state<state_slots(0), 0, MODE, TILED><<<grid, kStencilBlock, lds, stream>>>(sa);
+    else if (h == 1) k_pixel_state<state_slots(1), 1, MODE, TILED><<<grid, kStencilBlock, lds, stream>>>(sa);
+    else if (h == 2) k_pixel_state<state_slots(2), 2, MODE, TILED><<<grid, kStencilBlock, lds, stream>>>(sa);
+    else if (h <= 4) k_pixel_state<state_slots(4), -1, MODE, TILED><<<grid, kStencilBlock, lds, stream>>>(sa);
+    else k_pixel_state<state_slots(SS_MAX_PATCH / 2), -1, MODE, TILED><<<grid, kStencilBlock, lds, stream>>>(sa);
 }
 }  // namespace
 }  // namespace ss
@@ -1180,7 +1273,7 @@ extern "C" int ss_classify(const float *frames, const uint8_t *mask, int32_t n_f
         sa.snr_f = p->snr;
         sa.ws = ws;
         const int h = sa.half;
-        const size_t lds = size_t(kTileW + 2 * h) * size_t(kTileH + 2 * h) * 14;
+        const size_t lds = state_lds_bytes((kTileW + 2 * h) * (kTileH + 2 * h), state_slots(h));
         sa.tiles_x = (width + kTileW - 1) / kTileW;
         sa.tiles_y = (height + kTileH - 1) / kTileH;
         sa.frame_groups = (n_frames + kFramesPerBlock - 1) / kFramesPerBlock;
@@ -1189,13 +1282,15 @@ extern "C" int ss_classify(const float *frames, const uint8_t *mask, int32_t n_f
         if (items > (int64_t(1) << 31)) return SS_ESIZE;
         const dim3 grid(uint32_t(8 * ((items + 7) / 8)));
         // staging registers sized to the halo; patches 1, 3 and 5 unrolled;
-        // threshold lines when there is no noise level; tile-ordered staging
-        // for tiled frame layouts
-        const bool lines = p->noise == 0.0f;
-        if (lines && lay.tiled()) launch_pixel_state<true, true>(sa, h, grid, lds, stream);
-        else if (lines) launch_pixel_state<true, false>(sa, h, grid, lds, stream);
-        else if (lay.tiled()) launch_pixel_state<false, true>(sa, h, grid, lds, stream);
-        else launch_pixel_state<false, false>(sa, h, grid, lds, stream);
+        // threshold lines when there is no noise level (one line when
+        // n_pick == snr); tile-ordered staging for tiled frame layouts
+        const int mode = p->noise != 0.0f ? kModeBackground : p->n_pick == p->snr ? kModeLine : kModeLines;
+        if (mode == kModeLine && lay.tiled()) launch_pixel_state<kModeLine, true>(sa, h, grid, lds, stream);
+        else if (mode == kModeLine) launch_pixel_state<kModeLine, false>(sa, h, grid, lds, stream);
+        else if (mode == kModeLines && lay.tiled()) launch_pixel_state<kModeLines, true>(sa, h, grid, lds, stream);
+        else if (mode == kModeLines) launch_pixel_state<kModeLines, false>(sa, h, grid, lds, stream);
+        else if (lay.tiled()) launch_pixel_state<kModeBackground, true>(sa, h, grid, lds, stream);
+        else launch_pixel_state<kModeBackground, false>(sa, h, grid, lds, stream);
         SS_RETURN_IF_LAUNCH_FAILED();
     }
 

@@ -10,7 +10,10 @@
   for the azimuthal and the Poisson model (whose norm is rearranged too).
 * The whole path on tiled frames of the benchmark's batch (64 raw
   Jungfrau-4M frames) matches the FP64 oracle at the parity tolerance on
-  sampled frames, like the row-major path."""
+  sampled frames, like the row-major path.
+* With the same profile the classification of tiled frames is the
+  row-major one entry for entry (every threshold mode, unrolled and
+  runtime patches)."""
 
 import sys
 
@@ -139,3 +142,37 @@ def test_tiled_path_matches_oracle(dev, tiled_batch, f):
     got = pipe.frames[f].cpu().numpy()[words]
     assert np.array_equal(got.view(np.uint32), sc.corrected(signal)[0].view(np.uint32))
     _check_classify(sc, signal[0], pipe.profile, f, out, p, f"tiled batch frame {f}")
+
+
+@pytest.mark.parametrize("params", [
+    dict(),
+    dict(n_pick=1.0, snr=2.0, patch=5, min_count=4),
+    dict(n_pick=2.0, noise=1.0, patch=1, min_count=1),
+    dict(snr=-2.0, patch=7, min_count=3),
+    dict(n_pick=2.5, snr=2.5, patch=15, min_count=2),
+])
+def test_classify_on_tiled_frames_is_the_row_major_classification(dev, params):
+    """Same profile, same pixels: the classification of tiled frames (staged
+    tile by tile) is the row-major one, entry for entry, for one and two
+    threshold lines, a noise level, and unrolled and runtime patches."""
+    g = synth.SMALL
+    _say("case: classify on tiled frames, small-512 x8", params)
+    geo = api.Geometry.from_scene(g, synth.stripe_mask(g), synth.normalisation(g), dev)
+    geo_t = api.Geometry.from_scene(g, synth.stripe_mask(g), synth.normalisation(g), dev, tile=(8, 4))
+    frames = torch.from_numpy(synth.float_frames(g, 8).reshape(8, -1)).to(dev)
+    words = torch.from_numpy(_words_of(g.height, g.width, 8, 4)).to(dev)
+    frames_t = torch.full((8, geo_t.frame_words), float("nan"), device=dev)
+    frames_t[:, words] = frames
+    p = api.Params(**params)
+    prof = api.sigma_clip(frames, geo, p)
+    n_pix = g.height * g.width
+    ref = api.classify(frames, geo, prof, p, capacity=n_pix, peak_capacity=n_pix)
+    got = api.classify(frames_t, geo_t, prof, p, capacity=n_pix, peak_capacity=n_pix)
+    torch.cuda.synchronize()
+    assert torch.equal(got["n_kept"], ref["n_kept"]) and torch.equal(got["n_peaks"], ref["n_peaks"])
+    assert int(ref["n_peaks"].sum()) > 0
+    for f in range(8):
+        k, q = int(ref["n_kept"][f]), int(ref["n_peaks"][f])
+        assert torch.equal(got["kept_index"][f, :k], ref["kept_index"][f, :k])
+        assert torch.equal(got["kept_value"][f, :k].view(torch.int32), ref["kept_value"][f, :k].view(torch.int32))
+        assert torch.equal(got["peaks"][f, :q], ref["peaks"][f, :q])
