@@ -12,12 +12,13 @@
 // (v - mu > n_pick sigma_eff), peak candidate (v - mu >= snr sigma_eff) and
 // peak (the patch test of the peak finder, evaluated from LDS).
 //
-// Ordered output without atomics: tiles of consecutive pixels of one frame
-// (256 threads x 32 pixels; x 8 for one or two frames) count their kept
-// pixels and peaks (k_tile_counts), one work-group
-// per frame turns the counts into exclusive offsets (k_tile_scan), and the
-// tiles write their entries in pixel order at those offsets (k_tile_write),
-// computing peak records on the way.
+// Ordered output: the pixel pass also counts the kept pixels and peaks of
+// every compaction tile (consecutive pixels of one frame, 256 threads x 32
+// pixels; x 8 for one or two frames; integer sums, so the order of the
+// additions does not matter), one work-group per frame turns the counts
+// into exclusive offsets (k_tile_scan), and the tiles write their entries
+// in pixel order at those offsets (k_tile_write), computing peak records on
+// the way.
 //
 // The inverse direction (Sec. 3.2): k_densify rebuilds dense frames from the
 // same background table -- noise free, or with noise drawn from a
@@ -212,6 +213,8 @@ __global__ __launch_bounds__(kTableBlock) void k_profile_table(
         if (n_kept) n_kept[f] = 0;
         if (n_peaks) n_peaks[f] = 0;
     }
+    // the pixel pass adds every compaction tile's kept pixels and peaks
+    for (int t = tid; t < tiles; t += kTableBlock) ws.counts[int64_t(f) * tiles + t] = 0;
 }
 
 // ---- classification ----------------------------------------------------------
@@ -226,6 +229,7 @@ struct ClassArgs {
     int32_t height, width;
     int32_t n_bins;
     int32_t tiles;
+    int32_t counted;  // the pixel pass has counted the tiles (else k_tile_counts)
     double n_pick, snr, noise2;
     int32_t half, min_count;
     uint32_t *kept_index;
@@ -368,6 +372,10 @@ constexpr size_t state_head_bytes(int rn, int slots) {
     const size_t rc = size_t(rn) * 4, lists = 2 * kStateWaves * state_list_cap(slots) * sizeof(uint16_t);
     return ((rc > lists ? rc : lists) + 15) & ~size_t(15);
 }
+// compaction tiles one work-group of the pixel pass can count in LDS: its
+// kTileH rows of kTileW pixels span at most ((kTileH - 1) width + kTileW)
+// / tile + 2 of them
+constexpr int kTileCounters = 64;
 constexpr size_t state_lds_bytes(int rn, int slots) {
     return state_head_bytes(rn, slots) + size_t(slots) * kStencilBlock * 10;
 }
@@ -385,6 +393,8 @@ struct StateArgs {
     double noise2, n_pick, snr;
     float noise2f, n_pick_f, snr_f;
     int32_t tiles_x, tiles_y, frame_groups;
+    int32_t count_shift, count_tiles;  // compaction tiles: 2^count_shift pixels, count_tiles per frame
+    int32_t counting;                  // the pass adds the tiles' counts (else k_tile_counts does)
     Workspace ws;
 };
 
@@ -503,6 +513,10 @@ void k_pixel_state(StateArgs a) {
     uint8_t *b_base = lds + head + size_t(SN) * 8;
     constexpr int kCap = int(state_list_cap(kStageSlots));
     __shared__ uint32_t cnt_s[2][kStateWaves];
+    // kept pixels | peaks << 16 per compaction tile, from the work-group's
+    // first tile on, by frame parity (the host counts in a kernel of its own
+    // when a tile's rows span more compaction tiles)
+    __shared__ uint32_t tc_s[2][kTileCounters];
 
     // Work-groups go to the 8 XCDs round robin; work-group g takes item
     // (g % 8) * per + g / 8 of the row-major list (frame group, tile row,
@@ -527,6 +541,8 @@ void k_pixel_state(StateArgs a) {
     constexpr int kCore = kTileH * kTileW / kStencilBlock;
     // e / RW as (e * magic) >> 20, exact for e < 2^20 / RW (RN is far smaller)
     const uint32_t magic = ((1u << 20) + uint32_t(RW) - 1u) / uint32_t(RW);
+    const int first_tile = int((int64_t(ty0) * a.width + tx0) >> a.count_shift);
+    if (tid < 2 * kTileCounters) tc_s[tid / kTileCounters][tid % kTileCounters] = 0;
 
     for (int e = tid; e < RN; e += kStencilBlock) {
         const int r = int((uint32_t(e) * magic) >> 20);
@@ -574,20 +590,12 @@ void k_pixel_state(StateArgs a) {
         const bool core = e < RN && r >= h && r < h + kTileH && c >= h && c < h + kTileW;
         if (core) toff[k] |= kCand;
     }
-    // the tile's core pixels this thread stores: LDS index and offset in a
-    // frame (kNoPixel outside the frame)
-    static_assert(kTileH * kTileW % kStencilBlock == 0, "whole core pixels per thread");
-    constexpr uint32_t kNoPixel = 0xFFFFFFFFu;
-    uint32_t soff[kCore];
-    int cidx[kCore];
-#pragma unroll
-    for (int j = 0; j < kCore; ++j) {
-        const int c = tid + j * kStencilBlock;
-        const int ly = c / kTileW, lx = c % kTileW;
-        const int y = ty0 + ly, x = tx0 + lx;
-        soff[j] = (y < a.height && x < a.width) ? uint32_t(y) * uint32_t(a.width) + uint32_t(x) : kNoPixel;
-        cidx[j] = (ly + h) * RW + (lx + h);
-    }
+    // The tile's core pixels this thread stores: pixel j is core pixel
+    // tid + j * kStencilBlock, kCoreRows rows below pixel j - 1 in the same
+    // column, so its LDS index and its offset in a frame follow from those
+    // of pixel 0 (its row is the same for the whole wave).
+    static_assert(kTileH * kTileW % kStencilBlock == 0 && kStencilBlock % kTileW == 0, "whole core rows per slot");
+    constexpr int kCoreRows = kStencilBlock / kTileW;
     __syncthreads();  // the radial codes are dead; their bytes hold the lists
     // Only the last slot can lie wholly past the region for a wave (every
     // earlier slot index is below RN); such a wave skips it (its loads would
@@ -694,11 +702,32 @@ void k_pixel_state(StateArgs a) {
                 if (SS_SLOT_LIVE(k)) xv[k] = buffer_load_f32(rf, voff[k], 0u);
         }
         __syncthreads();
+        // the previous frame's tile counts are complete (added before this
+        // barrier): add them to the frame's, and clear them for frame f + 1
+        if (a.counting && f > f0 && tid < kTileCounters) {
+            const uint32_t v = tc_s[P ^ 1][tid];
+            if (v) atomicAdd(&a.ws.counts[int64_t(f - 1) * a.count_tiles + first_tile + tid], v);
+            tc_s[P ^ 1][tid] = 0;
+        }
+        auto count = [&](uint32_t p, uint32_t v) {
+            if (a.counting) atomicAdd(&tc_s[P][int(p >> a.count_shift) - first_tile], v);
+        };
         const __amdgpu_buffer_rsrc_t rb = buffer_rsrc(a.ws.bits + int64_t(f) * a.n_pix, uint32_t(a.n_pix));
+        // (formed here from the thread index: the width redefined per frame
+        // keeps them out of registers held across frames)
+        uint32_t width = uint32_t(a.width);
+        asm volatile("" : "+s"(width));
+        const int core_y0 = ty0 + tid / kTileW, core_x = tx0 + tid % kTileW;
+        const uint32_t soff0 = uint32_t(core_y0) * width + uint32_t(core_x);
+        const int cidx0 = (tid / kTileW + h) * RW + (tid % kTileW + h);
 #pragma unroll
         for (int j = 0; j < kCore; ++j) {
-            const uint8_t b = b_s[cidx[j]];
-            if (soff[j] != kNoPixel && (b & kCand) == 0) __builtin_amdgcn_raw_buffer_store_b8(b, rb, int(soff[j]), 0, 0);
+            const uint8_t b = b_s[cidx0 + j * kCoreRows * RW];
+            if (core_y0 + j * kCoreRows < a.height && uint32_t(core_x) < width) {
+                const uint32_t off = soff0 + uint32_t(j * kCoreRows) * width;
+                if ((b & kCand) == 0) __builtin_amdgcn_raw_buffer_store_b8(b, rb, int(off), 0, 0);
+                if (b & kKeep) count(off, 1u);
+            }
         }
         // candidate i of the work-group is entry i - p_w of wave w's list,
         // p_w the candidates of the waves before w: list slot
@@ -724,10 +753,17 @@ void k_pixel_state(StateArgs a) {
                 const bool peak = patch_is_peak<kH>(v_s, b_s, e, RW, h, a.min_count);
                 const int r = int((uint32_t(e) * magic) >> 20);
                 const uint32_t y = uint32_t(ty0 - h + r), x = uint32_t(tx0 - h + (e - r * RW));
-                __builtin_amdgcn_raw_buffer_store_b8(uint8_t(b_s[e] | (peak ? kPeak : 0)), rb,
-                                                     int(y * uint32_t(a.width) + x), 0, 0);
+                const uint32_t p = y * uint32_t(a.width) + x;
+                __builtin_amdgcn_raw_buffer_store_b8(uint8_t(b_s[e] | (peak ? kPeak : 0)), rb, int(p), 0, 0);
+                if (peak) count(p, 1u << 16);
             }
         }
+    }
+    // the last frame's tile counts
+    __syncthreads();
+    if (a.counting && f0 < f1 && tid < kTileCounters) {
+        const uint32_t v = tc_s[(f1 - 1 - f0) & 1][tid];
+        if (v) atomicAdd(&a.ws.counts[int64_t(f1 - 1) * a.count_tiles + first_tile + tid], v);
     }
 #undef SS_SLOT_LIVE
 }
@@ -823,7 +859,8 @@ __device__ inline uint32_t block_exclusive_scan(uint32_t mine, uint32_t *wave_to
     return before;
 }
 
-// Per tile: packed count of kept pixels and peaks (each at most kBlock * PPT).
+// Per tile: packed count of kept pixels and peaks (each at most kBlock * PPT),
+// for frames too wide for the pixel pass to count them.
 template <bool KEEP, bool PEAKS, int PPT>
 __global__ __launch_bounds__(kBlock) void k_tile_counts(ClassArgs a) {
     __shared__ uint32_t wave_tot[kNW];
@@ -954,7 +991,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_write(ClassArgs a) {
 template <bool KEEP, bool PEAKS, int PPT>
 void launch_compaction(const ClassArgs &a, hipStream_t stream) {
     const dim3 grid(uint32_t(a.tiles), uint32_t(a.n_frames));
-    k_tile_counts<KEEP, PEAKS, PPT><<<grid, kBlock, 0, stream>>>(a);
+    if (!a.counted) k_tile_counts<KEEP, PEAKS, PPT><<<grid, kBlock, 0, stream>>>(a);
     k_tile_scan<KEEP, PEAKS><<<dim3(uint32_t(a.n_frames)), kScanBlock, 0, stream>>>(a);
     k_tile_write<KEEP, PEAKS, PPT><<<grid, kBlock, 0, stream>>>(a);
 }
@@ -1252,6 +1289,7 @@ extern "C" int ss_classify(const float *frames, const uint8_t *mask, int32_t n_f
         pk ? n_peaks : nullptr, double(p->n_pick), double(p->snr));
     SS_RETURN_IF_LAUNCH_FAILED();
     if (tiles == 0) return SS_OK;
+    bool counted = false;
     {
         StateArgs sa;
         sa.frames = frames;
@@ -1272,6 +1310,11 @@ extern "C" int ss_classify(const float *frames, const uint8_t *mask, int32_t n_f
         sa.n_pick_f = p->n_pick;
         sa.snr_f = p->snr;
         sa.ws = ws;
+        const int64_t tile_px = int64_t(kBlock) * (few ? kPPTFew : kPPT);
+        sa.count_shift = __builtin_ctz(uint32_t(tile_px));
+        sa.count_tiles = tiles;
+        sa.counting = (int64_t(kTileH - 1) * width + kTileW) / tile_px + 2 <= kTileCounters;
+        counted = sa.counting != 0;
         const int h = sa.half;
         const size_t lds = state_lds_bytes((kTileW + 2 * h) * (kTileH + 2 * h), state_slots(h));
         sa.tiles_x = (width + kTileW - 1) / kTileW;
@@ -1305,6 +1348,7 @@ extern "C" int ss_classify(const float *frames, const uint8_t *mask, int32_t n_f
     a.width = width;
     a.n_bins = radial->n_bins;
     a.tiles = tiles;
+    a.counted = counted ? 1 : 0;
     a.n_pick = double(p->n_pick);
     a.snr = double(p->snr);
     a.noise2 = double(p->noise) * double(p->noise);

@@ -403,6 +403,38 @@ def test_dense_candidates(dev, snr, patch):
         assert rp.size > 10, rp.size
 
 
+@pytest.mark.parametrize("n_frames", [1, 3])
+def test_wide_frames_match_oracle(dev, n_frames):
+    """Frames 9000 pixels wide: one frame counts its compaction tiles in a
+    kernel of its own (a pixel-pass tile's rows span more tiles than the
+    pass counts in LDS), three frames count them in the pixel pass; kept
+    pixels and peaks equal to the oracle's either way."""
+    _say("case: wide frames", n_frames)
+    H, W = 20, 9000
+    rng = np.random.default_rng(47)
+    from oracle import geometry as OG
+    from oracle import classify as OKc
+    frames = rng.poisson(40.0, (n_frames, H * W)).astype(np.float32)
+    geo = api.Geometry(H, W, 75e-6, 0.01, 10.3, 4500.1, 16, "bbox", None, None, dev)
+    csr = OG.build_csr(H, W, 75e-6, 0.01, 10.3, 4500.1, 16, "bbox")
+    pos = OG.centre_angle(H, W, 75e-6, 0.01, 10.3, 4500.1)
+    p = api.Params(snr=2.0, min_count=2)
+    fr = torch.from_numpy(frames).to(dev)
+    prof = api.sigma_clip(fr, geo, p)
+    out = api.classify(fr, geo, prof, p, capacity=H * W, peak_capacity=H * W)
+    torch.cuda.synchronize()
+    for f in range(n_frames):
+        ref, _ = P.compare_profile(_prof_host(prof, f), frames[f], None, csr, None, p, *P.input_eps(None, "bbox"),
+                                   f"wide {f}")
+        ri, _ = OKc.compress(frames[f], None, pos, csr.centres, ref, 3.0)
+        n = int(out["n_kept"][f])
+        assert n == ri.size and np.array_equal(out["kept_index"][f, :n].cpu().numpy(), ri)
+        rp = OKc.peakfind(frames[f], None, H, W, pos, csr.centres, ref, 2.0, 3, 2)
+        gp = api.peaks_to_numpy(out["peaks"][f], int(out["n_peaks"][f]))
+        assert np.array_equal(gp["index"].astype(np.int64), rp["index"]), (f, gp.size, rp.size)
+        assert rp.size > 10 and ri.size > 100, (rp.size, ri.size)
+
+
 def test_correct_indexed_matches_correct(dev, jungfrau):
     """ss_correct_indexed: frames picked from a ring by a device index are
     corrected bit for bit as ss_correct corrects the same frames; an index
