@@ -706,7 +706,9 @@ void k_pixel_state(StateArgs a) {
         // barrier): add them to the frame's, and clear them for frame f + 1
         if (a.counting && f > f0 && tid < kTileCounters) {
             const uint32_t v = tc_s[P ^ 1][tid];
-            if (v) atomicAdd(&a.ws.counts[int64_t(f - 1) * a.count_tiles + first_tile + tid], v);
+            int t0 = first_tile;
+            asm volatile("" : "+s"(t0));  // the address formed here, not held across frames
+            if (v) atomicAdd(&a.ws.counts[int64_t(f - 1) * a.count_tiles + t0 + tid], v);
             tc_s[P ^ 1][tid] = 0;
         }
         auto count = [&](uint32_t p, uint32_t v) {
