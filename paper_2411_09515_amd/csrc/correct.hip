@@ -46,16 +46,20 @@ constexpr int kVec = 4;
 constexpr int kCorrectBlock = SS_CORRECT_BLOCK;
 
 // float32(a / b) rounded to nearest, for a and b exact in float64, given
-// r = float64(1 / b).  The product a * r lies within |q| * 2^-51 of a / b, so
-// when q - d and q + d (d = |q| * 2^-50) round to the same float32, a / b
-// rounds to it too; otherwise (a / b within 2^-50 of a float32 rounding
-// boundary, about one value in 10^8) the exact quotient is formed.
+// r = float64(1 / b).  The product q = a * r lies within 2^-52 |a / b| (1 +
+// 2^-52) of a / b: two units in q's last place.  Rounding to float32 keeps
+// q's top 24 significant bits and decides on the 29 fraction bits below,
+// whose only rounding boundary is the half-way pattern 2^28 (values just
+// either side of a float32 itself round to it).  So when those 29 bits lie
+// more than 8 from 2^28, a / b rounds as q does; otherwise (about one value
+// in 3 * 10^7) the exact quotient is formed.
+__device__ __noinline__ float div_exact32(double a, float b) { return float(a / double(b)); }
+
 __device__ inline float div_round32(double a, float b, double r) {
     const double q = a * r;
-    const double d = fabs(q) * 0x1p-50;
-    const float lo = float(q - d);
-    const float hi = float(q + d);
-    return lo == hi ? lo : float(a / double(b));
+    const uint32_t below = uint32_t(uint64_t(__double_as_longlong(q))) & 0x1FFFFFFFu;
+    if (__builtin_expect(below - (0x10000000u - 8u) > 16u, 1)) return float(q);
+    return div_exact32(a, b);
 }
 
 // Calibration of one pixel held in registers for the whole batch: the three
