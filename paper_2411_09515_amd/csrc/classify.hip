@@ -772,37 +772,6 @@ void k_pixel_state(StateArgs a) {
 
 // ---- peak test and record ------------------------------------------------------------
 
-struct PeakSums {
-    int count;
-    double I, s2, sy, sx;
-};
-
-// Record of peak i over the candidates of its patch (background recomputed
-// from the table: peaks are rare).
-__device__ PeakSums peak_record(const ClassArgs &a, const float *__restrict__ fr, const uint8_t *__restrict__ bits,
-                                const Seg *__restrict__ tab, int64_t i) {
-    const int y = int(i / a.width);
-    const int x = int(i - int64_t(y) * a.width);
-    const int y0 = max(0, y - a.half), y1 = min(a.height - 1, y + a.half);
-    const int x0 = max(0, x - a.half), x1 = min(a.width - 1, x + a.half);
-    PeakSums ps{0, 0.0, 0.0, 0.0, 0.0};
-    for (int yy = y0; yy <= y1; ++yy) {
-        for (int xx = x0; xx <= x1; ++xx) {
-            const int64_t j = int64_t(yy) * a.width + xx;
-            if (!(bits[j] & kCand)) continue;
-            double mu, se;
-            background(a.rcoord[j], tab, a.n_bins, a.noise2, mu, se);
-            const double d = double(fr[a.lay.offset(yy, xx)]) - mu;
-            ps.count += 1;
-            ps.I += d;
-            ps.s2 += se * se;
-            ps.sy += d * (double(yy) + 0.5);
-            ps.sx += d * (double(xx) + 0.5);
-        }
-    }
-    return ps;
-}
-
 // Inclusive prefix sum over the 64 lanes of a wavefront.
 __device__ inline uint32_t wave_inclusive_scan(uint32_t x) {
     const int lane = threadIdx.x & (kWave - 1);
@@ -968,24 +937,59 @@ __global__ __launch_bounds__(kBlock) void k_tile_write(ClassArgs a) {
             }
         }
     }
-    if (PEAKS && pmask) {
+    if (PEAKS) {
+        // The wave's peaks one at a time, every lane taking one pixel of the
+        // patch (patches of more than 64 pixels in rounds): a record costs
+        // two rounds of dependent loads instead of three per neighbour, and
+        // the lanes without peaks no longer wait for the one that has them.
+        // The sums over the patch are the wave's reductions, in a fixed order.
         const Seg *__restrict__ tab = a.ws.table + int64_t(f) * (a.n_bins + 1);
-        uint32_t m = pmask;
-        while (m) {
-            const int k = __builtin_ctz(m);
-            m &= m - 1;
-            if (pos_p < a.peak_capacity) {
-                const int64_t i = p0 + k;
-                const PeakSums ps = peak_record(a, fr, bits, tab, i);
-                ss_peak rec;
-                rec.index = uint32_t(i);
-                rec.y = float(ps.sy / ps.I);
-                rec.x = float(ps.sx / ps.I);
-                rec.intensity = float(ps.I);
-                rec.sigma = float(sqrt(ps.s2));
-                a.peaks[int64_t(f) * a.peak_capacity + pos_p] = rec;
+        const int lane = threadIdx.x & (kWave - 1);
+        const int P = 2 * a.half + 1;
+        uint64_t owners = __builtin_amdgcn_ballot_w64(pmask != 0);
+        while (owners) {
+            const int src = __builtin_ctzll(owners);
+            owners &= owners - 1;
+            uint32_t m = uint32_t(__builtin_amdgcn_readlane(int(pmask), src));
+            int64_t pos = (int64_t(__builtin_amdgcn_readlane(int(uint64_t(pos_p) >> 32), src)) << 32) |
+                          int64_t(uint32_t(__builtin_amdgcn_readlane(int(uint32_t(pos_p)), src)));
+            const int64_t p_src = (int64_t(tile) * kBlock + (threadIdx.x - lane) + src) * PPT;
+            while (m) {
+                const int k = __builtin_ctz(m);
+                m &= m - 1;
+                if (pos < a.peak_capacity) {
+                    const int64_t i = p_src + k;
+                    const int y = int(i / a.width), x = int(i - int64_t(i / a.width) * a.width);
+                    double sums[4] = {0.0, 0.0, 0.0, 0.0};  // I, s2, sy, sx
+                    for (int base = 0; base < P * P; base += kWave) {
+                        const int q = base + lane;
+                        const int yy = y + q / P - a.half, xx = x + q % P - a.half;
+                        if (q < P * P && yy >= 0 && yy < a.height && xx >= 0 && xx < a.width) {
+                            const int64_t j = int64_t(yy) * a.width + xx;
+                            if (bits[j] & kCand) {
+                                double mu, se;
+                                background(a.rcoord[j], tab, a.n_bins, a.noise2, mu, se);
+                                const double d = double(fr[a.lay.offset(yy, xx)]) - mu;
+                                sums[0] += d;
+                                sums[1] += se * se;
+                                sums[2] += d * (double(yy) + 0.5);
+                                sums[3] += d * (double(xx) + 0.5);
+                            }
+                        }
+                    }
+                    wave_sum_last_n(sums);
+                    if (lane == kWave - 1) {
+                        ss_peak rec;
+                        rec.index = uint32_t(i);
+                        rec.y = float(sums[2] / sums[0]);
+                        rec.x = float(sums[3] / sums[0]);
+                        rec.intensity = float(sums[0]);
+                        rec.sigma = float(sqrt(sums[1]));
+                        a.peaks[int64_t(f) * a.peak_capacity + pos] = rec;
+                    }
+                }
+                ++pos;
             }
-            ++pos_p;
         }
     }
 }
