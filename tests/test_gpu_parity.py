@@ -370,12 +370,13 @@ def test_tiny_ragged_frame(dev):
     assert int(out["n_peaks"][0]) >= 1
 
 
-@pytest.mark.parametrize("snr,patch", [(0.0, 3), (-2.0, 3), (-2.0, 5), (-2.0, 7)])
+@pytest.mark.parametrize("snr,patch", [(0.0, 3), (-2.0, 3), (-2.0, 5), (-2.0, 7), (-2.0, 9)])
 def test_dense_candidates(dev, snr, patch):
     """Most pixels are candidates (snr <= 0): each wave's list of candidate
     core pixels holds well over 64 entries and takes several rounds of patch
-    tests; unrolled (3 x 3, 5 x 5) and runtime (7 x 7) patches, kept pixels
-    and peaks equal to the oracle's."""
+    tests; unrolled (3 x 3, 5 x 5) and runtime (7 x 7, 9 x 9: a patch of more
+    than 64 pixels, whose records take two rounds of the wave) patches, kept
+    pixels and peaks equal to the oracle's, records within 1e-5."""
     _say("case: dense candidates", snr, patch)
     H, W = 70, 150
     rng = np.random.default_rng(31)
@@ -401,6 +402,13 @@ def test_dense_candidates(dev, snr, patch):
         gp = api.peaks_to_numpy(out["peaks"][f], int(out["n_peaks"][f]))
         assert np.array_equal(gp["index"].astype(np.int64), rp["index"]), (f, gp.size, rp.size)
         assert rp.size > 10, rp.size
+        # with candidates below the background (snr < 0) the intensity of a
+        # patch may nearly cancel, so the centroid (a ratio) is compared
+        # through its numerator
+        gi, ri = gp["intensity"].astype(np.float64), rp["intensity"]
+        for a, b, k in ((gi, ri, "intensity"), (gp["sigma"].astype(np.float64), rp["sigma"], "sigma"),
+                        (gp["y"] * gi, rp["y"] * ri, "y * intensity"), (gp["x"] * gi, rp["x"] * ri, "x * intensity")):
+            assert np.allclose(a, b, rtol=2e-6, atol=1e-6 * np.abs(b).max()), (f, k)
 
 
 @pytest.mark.parametrize("n_frames", [1, 3])
