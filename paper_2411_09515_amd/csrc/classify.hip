@@ -404,7 +404,8 @@ struct StateArgs {
 // candidate), computed once per staged pixel.  Candidates of the tile then
 // take the patch test of Sec. 4 from LDS (maximum of v over the valid
 // pixels of the patch, ties to the lower index; at least min_count
-// candidates) and the bits, with kPeak, go to the workspace.
+// candidates) and the bits, with kPeak, go to the workspace; the kept
+// pixels and peaks of every compaction tile are counted on the way.
 // Patch test of Sec. 4 from LDS for candidate e: v must be the maximum over
 // the valid pixels of the patch (ties to the lower row-major index, i.e. a
 // neighbour above, or on the same row to the left, wins a tie) with at least
@@ -619,7 +620,9 @@ void k_pixel_state(StateArgs a) {
     // candidates take the patch test 64 per wave (batches rotated over the
     // waves by frame, so one wave tests a tile's usual few dozen), each
     // tester stores its candidate's state byte, and the owners of the other
-    // core pixels store theirs: every byte is written once.
+    // core pixels store theirs: every byte is written once.  Owners count
+    // kept pixels and testers peaks into LDS counters of the frame's
+    // parity, which go to memory after the next frame's barrier.
     for (int f = f0; f < f1; ++f) {
         const int P = (f - f0) & 1;
         float *v_s = v_base + P * SN;
